@@ -1,0 +1,232 @@
+"""Exact-distribution pins of O1 (random-sequential update) and O2 (2x2-block
+schedule) on tiny lattices.
+
+The exact distributions are built here by brute-force enumeration from the
+paper's description of one elementary step (Sec. "Single Threaded ESCG in
+C++": a uniform cell, a uniform one of its four von Neumann neighbours under
+periodic wrap, an action with probabilities proportional to the rates, then
+the action's prose semantics).  The oracles are sampled with independent
+streams (replica ids) and compared by a G-test.
+
+* L = 2: every site's left and right (and up and down) neighbour coincide,
+  the lattice has exactly four edges, each chosen with probability 1/4 and a
+  uniform orientation.  One O2 pass uses one 2x2 block that covers the
+  lattice and picks one of the same four edges, so one O2 MCS (four passes)
+  has the law of four RSU steps.
+* L = 3: the RSU chain on 4^9 states with distinct up/down/left/right.
+* L = 4: one O2 pass is a uniform mixture over the four block offsets of
+  independent per-block updates.
+"""
+import itertools
+
+import numpy as np
+import pytest
+from scipy.stats import chi2
+
+import oracle as O
+from tests.test_oracle_rule import _prose_rule
+
+
+def g_test(observed: dict, expected_p: dict, n: int, min_e: float = 5.0):
+    """G-test p-value of observed counts against exact probabilities, with
+    categories of small expectation pooled into one."""
+    keys = set(expected_p) | set(observed)
+    for k in observed:
+        assert expected_p.get(k, 0.0) > 0.0, f"impossible outcome {k}"
+    big = [k for k in keys if expected_p.get(k, 0.0) * n >= min_e]
+    small = [k for k in keys if k not in set(big)]
+    obs = [observed.get(k, 0) for k in big]
+    exp = [expected_p[k] * n for k in big]
+    if small:
+        obs.append(sum(observed.get(k, 0) for k in small))
+        exp.append(sum(expected_p.get(k, 0.0) for k in small) * n)
+    obs = np.array(obs, float)
+    exp = np.array(exp, float)
+    m = obs > 0
+    G = 2.0 * np.sum(obs[m] * np.log(obs[m] / exp[m]))
+    df = max(len(obs) - 1, 1)
+    return chi2.sf(G, df)
+
+
+def rsu_step_dist(L, S, D, rates, dist):
+    """One random-sequential step applied to a distribution over lattices
+    (dict tuple -> prob).  Neighbours: up, down, left, right with wrap."""
+    ex, sel, rep = rates
+    tot = ex + sel + rep
+    pa = {O.EXCHANGE: ex / tot, O.SELECTION: sel / tot,
+          O.REPRODUCTION: rep / tot}
+    N = L * L
+    out = {}
+    for state, p in dist.items():
+        for i in range(N):
+            r, c = divmod(i, L)
+            for nr, nc in (((r - 1) % L, c), ((r + 1) % L, c),
+                           (r, (c - 1) % L), (r, (c + 1) % L)):
+                j = nr * L + nc
+                for a, q in pa.items():
+                    if q == 0.0:
+                        continue
+                    s = list(state)
+                    s[i], s[j] = _prose_rule(a, s[i], s[j], D)
+                    t = tuple(s)
+                    out[t] = out.get(t, 0.0) + p * q / (4 * N)
+    return out
+
+
+def sample(fn, n):
+    hist = {}
+    for rep in range(n):
+        t = tuple(int(v) for v in fn(rep))
+        hist[t] = hist.get(t, 0) + 1
+    return hist
+
+
+RATES = [(1.0, 1.0, 2.0), (0.5, 1.0, 1.0)]
+# An imported, non-antisymmetric matrix (1 and 2 beat each other, 3 beats 1):
+# here the orientation of the chosen pair matters.
+D_MUTUAL = np.array([[0, 1, 0], [1, 0, 0], [1, 0, 0]], np.uint8)
+
+
+@pytest.mark.parametrize("rates", RATES)
+@pytest.mark.parametrize("mutual", [False, True])
+def test_L2_rsu_matches_exact_chain(rates, mutual):
+    L, S = 2, 3
+    D = D_MUTUAL if mutual else O.circulant_matrix(S, [1])
+    g0 = np.array([1, 2, 0, 3], np.uint8)
+    steps = 4
+    dist = {tuple(g0.tolist()): 1.0}
+    for _ in range(steps):
+        dist = rsu_step_dist(L, S, D, rates, dist)
+    n = 20000
+
+    def run(rep):
+        job = O.Job(L, S, D, *rates, seed=11, replica=rep)
+        g = g0.copy()
+        O.o1_steps(job, g, 0, steps)
+        return g
+    assert g_test(sample(run, n), dist, n) > 1e-4
+
+
+@pytest.mark.parametrize("rates", RATES)
+@pytest.mark.parametrize("mutual", [False, True])
+def test_L2_block_schedule_mcs_equals_four_rsu_steps(rates, mutual):
+    L, S = 2, 3
+    D = D_MUTUAL if mutual else O.circulant_matrix(S, [1])
+    g0 = np.array([3, 0, 2, 1], np.uint8)
+    dist = {tuple(g0.tolist()): 1.0}
+    for _ in range(8):
+        dist = rsu_step_dist(L, S, D, rates, dist)
+    n = 20000
+
+    def run(rep):
+        job = O.Job(L, S, D, *rates, seed=5, replica=rep)
+        g = g0.copy()
+        O.o2_run(job, g, 17, 2, want_counts=False)  # two MCS = 8 passes
+        return g
+    assert g_test(sample(run, n), dist, n) > 1e-4
+
+
+def test_L3_rsu_matches_exact_chain():
+    L, S = 3, 3
+    D = O.circulant_matrix(S, [1])
+    rates = (1.0, 1.0, 2.0)
+    g0 = np.array([1, 2, 3, 0, 1, 2, 3, 0, 2], np.uint8)
+    steps = 3
+    dist = {tuple(g0.tolist()): 1.0}
+    for _ in range(steps):
+        dist = rsu_step_dist(L, S, D, rates, dist)
+    n = 30000
+
+    def run(rep):
+        job = O.Job(L, S, D, *rates, seed=3, replica=rep)
+        g = g0.copy()
+        O.o1_steps(job, g, 1000, steps)
+        return g
+    assert g_test(sample(run, n), dist, n) > 1e-4
+
+
+def block_pass_dist(L, S, D, rates, g0):
+    """Exact law of one O2 pass from g0: offsets uniform on {0,1}^2; the
+    (L/2)^2 disjoint 2x2 blocks update independently, each on a uniform one
+    of its 4 internal edges with a uniform orientation and an action drawn
+    with probability proportional to the rates."""
+    ex, sel, rep = rates
+    tot = ex + sel + rep
+    pa = [(O.EXCHANGE, ex / tot), (O.SELECTION, sel / tot),
+          (O.REPRODUCTION, rep / tot)]
+    total = {}
+    for ox, oy in itertools.product((0, 1), repeat=2):
+        per_block = []
+        for by, bx in itertools.product(range(L // 2), repeat=2):
+            r0, c0 = 2 * by + oy, 2 * bx + ox
+            r1, c1 = (r0 + 1) % L, (c0 + 1) % L
+            A, B, C_, Dd = (r0 * L + c0, r0 * L + c1, r1 * L + c0,
+                            r1 * L + c1)
+            sites = (A, B, C_, Dd)
+            outcomes = {}
+            for (f, s) in ((A, B), (C_, Dd), (A, C_), (B, Dd)):
+                for cell, nbr in ((f, s), (s, f)):
+                    for a, q in pa:
+                        loc = {k: int(g0[k]) for k in sites}
+                        loc[cell], loc[nbr] = _prose_rule(a, loc[cell],
+                                                          loc[nbr], D)
+                        key = tuple(loc[k] for k in sites)
+                        outcomes[key] = outcomes.get(key, 0.0) + q / 8
+            per_block.append((sites, outcomes))
+        joint = {tuple(g0.tolist()): 1.0}
+        for sites, outcomes in per_block:
+            nxt = {}
+            for st, p in joint.items():
+                for vals, q in outcomes.items():
+                    s = list(st)
+                    for k, v in zip(sites, vals):
+                        s[k] = v
+                    t = tuple(s)
+                    nxt[t] = nxt.get(t, 0.0) + p * q
+            joint = nxt
+        for st, p in joint.items():
+            total[st] = total.get(st, 0.0) + p / 4
+    return total
+
+
+@pytest.mark.parametrize("mutual", [False, True])
+def test_L4_one_pass_matches_exact_block_law(mutual):
+    L, S = 4, 3
+    D = D_MUTUAL if mutual else O.circulant_matrix(S, [1])
+    rates = (1.0, 1.0, 2.0)
+    g0 = np.array([1, 2, 0, 3,
+                   3, 3, 1, 0,
+                   0, 2, 2, 1,
+                   1, 0, 3, 2], np.uint8)
+    dist = block_pass_dist(L, S, D, rates, g0)
+    assert abs(sum(dist.values()) - 1.0) < 1e-9
+    n = 40000
+
+    def run(rep):
+        job = O.Job(L, S, D, *rates, seed=9, replica=rep)
+        g = g0.copy()
+        O.o2_pass(job, g, 3, rep % 4)
+        return g
+    assert g_test(sample(run, n), dist, n) > 1e-4
+
+
+def test_g_test_detects_a_planted_rule_error():
+    # Sanity of the harness itself: the exact L=2 law with reproduction
+    # swapped for a no-op must be rejected against real O1 samples.
+    L, S = 2, 3
+    D = O.circulant_matrix(S, [1])
+    rates = (1.0, 1.0, 2.0)
+    g0 = np.array([1, 2, 0, 3], np.uint8)
+    wrong = {tuple(g0.tolist()): 1.0}
+    for _ in range(4):
+        wrong = rsu_step_dist(L, S, D, (1.0, 1.0, 0.0), wrong)
+    n = 5000
+
+    def run(rep):
+        job = O.Job(L, S, D, *rates, seed=11, replica=rep)
+        g = g0.copy()
+        O.o1_steps(job, g, 0, 4)
+        return g
+    obs = sample(run, n)
+    wrong = {k: wrong.get(k, 0.0) + 1e-12 for k in set(wrong) | set(obs)}
+    assert g_test(obs, wrong, n) < 1e-6

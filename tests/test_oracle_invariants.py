@@ -1,0 +1,154 @@
+"""Invariants both oracles must satisfy (conservation, absorbing states,
+monotone empties, label symmetry, resume), checked on random lattices."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2508_16639_amd.workloads import random_lattice
+
+RUNNERS = {"O1": O.o1_run, "O2": O.o2_run}
+
+
+def _job(L, S, K, ex=0.7, sel=1.0, rep=1.0, seed=3, replica=0, D=None):
+    if D is None:
+        D = O.circulant_matrix(S, K)
+    return O.Job(L, S, D, ex, sel, rep, seed=seed, replica=replica)
+
+
+@pytest.mark.parametrize("which", ["O1", "O2"])
+@pytest.mark.parametrize("S,K", [(3, [1]), (5, [1, 3])])
+def test_counts_conserve_sites_and_values_stay_in_range(which, S, K):
+    L = 24
+    job = _job(L, S, K)
+    g = job.init()
+    c0 = O.counts(g, L, S)
+    c = RUNNERS[which](job, g, 0, 30)
+    assert (c[0] == c0).all()
+    assert (c.sum(1) == L * L).all()                 # I1
+    assert g.max() <= S                              # I2
+    assert (c[-1] == O.counts(g, L, S)).all()
+    # I3: once a species is gone it never comes back (no mutation)
+    for s in range(1, S + 1):
+        z = np.nonzero(c[:, s] == 0)[0]
+        if z.size:
+            assert (c[z[0]:, s] == 0).all()
+
+
+@pytest.mark.parametrize("which", ["O1", "O2"])
+def test_exchange_only_permutes_sites(which):
+    L, S = 16, 5
+    job = _job(L, S, [1, 3], ex=1.0, sel=0.0, rep=0.0)
+    g = random_lattice(L, S, seed=4)
+    before = np.sort(g.copy())
+    c = RUNNERS[which](job, g, 5, 40)
+    assert (c == c[0]).all()                         # I4 counts exact
+    assert np.array_equal(np.sort(g), before)        # I4 permutation
+    assert not np.array_equal(g, random_lattice(L, S, seed=4))
+
+
+@pytest.mark.parametrize("which", ["O1", "O2"])
+@pytest.mark.parametrize("fill", [0, 1, 2])
+def test_uniform_lattices_are_absorbing(which, fill):
+    L, S = 12, 3
+    job = _job(L, S, [1])
+    g = np.full(L * L, fill, np.uint8)
+    RUNNERS[which](job, g, 0, 20, want_counts=False)
+    assert (g == fill).all()                         # I5
+
+
+@pytest.mark.parametrize("which", ["O1", "O2"])
+def test_empty_count_monotone_under_single_actions(which):
+    L, S = 20, 3
+    g0 = random_lattice(L, S, seed=8)
+    job = _job(L, S, [1], ex=0.0, sel=0.0, rep=1.0)
+    c = RUNNERS[which](job, g0.copy(), 0, 15)
+    assert (np.diff(c[:, 0].astype(np.int64)) <= 0).all()   # I6 reproduction
+    job = _job(L, S, [1], ex=0.0, sel=1.0, rep=0.0)
+    c = RUNNERS[which](job, g0.copy(), 0, 15)
+    assert (np.diff(c[:, 0].astype(np.int64)) >= 0).all()   # I6 selection
+
+
+@pytest.mark.parametrize("which", ["O1", "O2"])
+@pytest.mark.parametrize("S,K", [(3, [1]), (5, [1, 3])])
+def test_cyclic_relabel_commutes_bit_exactly(which, S, K):
+    # i -> i+1 (mod S) on species, 0 fixed, is an automorphism of C(S, K);
+    # the random draws do not depend on labels, so the runs map exactly.  (I7)
+    L = 16
+    job = _job(L, S, K, ex=0.9)
+    g = random_lattice(L, S, seed=21)
+    rot = np.array([0] + [(s % S) + 1 for s in range(1, S + 1)], np.uint8)
+    a = g.copy()
+    RUNNERS[which](job, a, 2, 12, want_counts=False)
+    b = rot[g]
+    RUNNERS[which](job, b, 2, 12, want_counts=False)
+    assert np.array_equal(rot[a], b)
+
+
+@pytest.mark.parametrize("which", ["O1", "O2"])
+def test_rpsls_offset_sets_are_isomorphic(which):
+    # phi(s) = 1 + (3 (s-1) mod 5), phi(0) = 0 maps C(5,{1,2}) onto
+    # C(5,{1,3}), so run_{1,3}(phi g) == phi(run_{1,2}(g)).  (I8)
+    L, S = 16, 5
+    phi = np.array([0] + [1 + (3 * (s - 1)) % 5 for s in range(1, 6)], np.uint8)
+    j12 = _job(L, S, [1, 2], ex=0.4, seed=9)
+    j13 = _job(L, S, [1, 3], ex=0.4, seed=9)
+    D12, D13 = O.circulant_matrix(5, [1, 2]), O.circulant_matrix(5, [1, 3])
+    for a in range(1, 6):
+        for b in range(1, 6):
+            assert D12[a - 1, b - 1] == D13[phi[a] - 1, phi[b] - 1]
+    g = random_lattice(L, S, seed=2)
+    a = g.copy()
+    RUNNERS[which](j12, a, 0, 10, want_counts=False)
+    b = phi[g]
+    RUNNERS[which](j13, b, 0, 10, want_counts=False)
+    assert np.array_equal(phi[a], b)
+
+
+@pytest.mark.parametrize("which", ["O1", "O2"])
+def test_resume_split_equals_straight_run(which):
+    L, S = 20, 3
+    job = _job(L, S, [1])
+    g = job.init()
+    a = g.copy()
+    ca = RUNNERS[which](job, a, 0, 25)
+    b = g.copy()
+    cb1 = RUNNERS[which](job, b, 0, 11)
+    cb2 = RUNNERS[which](job, b, 11, 14)             # I10
+    assert np.array_equal(a, b)
+    assert np.array_equal(ca, np.vstack([cb1, cb2[1:]]))
+
+
+@pytest.mark.parametrize("mode", [O.FIRST_EXTINCTION, O.MONOCULTURE])
+@pytest.mark.parametrize("which", ["O1", "O2"])
+def test_run_until_agrees_with_plain_run(mode, which):
+    L, S, cap = 8, 3, 400
+    until = {"O1": O.o1_run_until, "O2": O.o2_run_until}[which]
+    hits = 0
+    for rep in range(12):
+        job = _job(L, S, [1], ex=2.0, replica=rep)
+        g = job.init()
+        ref = g.copy()
+        c = RUNNERS[which](job, ref, 0, cap)
+        alive = (c[:, 1:] > 0).sum(1)
+        cond = alive < S if mode == O.FIRST_EXTINCTION else alive <= 1
+        r = until(job, g, 0, cap, mode)
+        if cond.any():
+            t = int(np.argmax(cond))
+            hits += 1
+            assert r[0] == 1 and r[1] == t
+            assert (r[2:] == c[t]).all()
+            again = job.init()
+            RUNNERS[which](job, again, 0, t, want_counts=False)
+            assert np.array_equal(again, g)
+        else:
+            assert r[0] == 0 and r[1] == cap and (r[2:] == c[-1]).all()
+    assert hits > 0
+
+
+def test_run_until_input_already_extinct_returns_t0():
+    L, S = 8, 3
+    job = _job(L, S, [1])
+    g = np.zeros(L * L, np.uint8)
+    g[:5] = 1
+    r = O.o2_run_until(job, g, 0, 50, O.FIRST_EXTINCTION)
+    assert r[0] == 1 and r[1] == 0 and r[2 + 1] == 5

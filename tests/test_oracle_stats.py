@@ -1,0 +1,55 @@
+"""Statistical agreement of the block schedule (O2) with the paper's
+random-sequential update (O1) on RPS, beyond the exact small-lattice laws.
+
+Tolerances: differences of means within 4 standard errors of the difference
+(floor 0.005 for densities); deterministic seeds, so the outcome is fixed."""
+from multiprocessing import Pool
+
+import numpy as np
+from scipy.stats import ks_2samp
+
+import oracle as O
+from paper_2508_16639_amd.workloads import eps_from_mobility
+
+
+def _extinction(args):
+    which, L, M, rep = args
+    job = O.Job(L, 3, O.circulant_matrix(3, [1]), eps_from_mobility(M, L),
+                seed=1, replica=rep)
+    g = job.init()
+    f = O.o2_run_until if which == 2 else O.o1_run_until
+    r = f(job, g, 0, 20 * L, O.FIRST_EXTINCTION)
+    return int(r[0]), int(r[1])
+
+
+def _densities(args):
+    which, L, M, T, rep = args
+    job = O.Job(L, 3, O.circulant_matrix(3, [1]), eps_from_mobility(M, L),
+                seed=2, replica=rep)
+    g = job.init()
+    f = O.o2_run if which == 2 else O.o1_run
+    c = f(job, g, 0, T)
+    return c[T // 2:].mean(0) / (L * L)
+
+
+def test_extinction_probability_o1_vs_o2():
+    L, M, R = 32, 1e-3, 2000
+    with Pool(8) as p:
+        r2 = np.array(p.map(_extinction, [(2, L, M, i) for i in range(R)]))
+        r1 = np.array(p.map(_extinction, [(1, L, M, i) for i in range(R)]))
+    p1, p2 = r1[:, 0].mean(), r2[:, 0].mean()
+    assert 0.2 < p1 < 0.8
+    se = np.sqrt(p1 * (1 - p1) / R + p2 * (1 - p2) / R)
+    assert abs(p1 - p2) <= 4 * se, (p1, p2, se)
+    # times to extinction (censored at the cap) have the same law
+    assert ks_2samp(r1[:, 1], r2[:, 1]).pvalue > 1e-4
+
+
+def test_mean_densities_o1_vs_o2():
+    L, M, T, R = 64, 1e-5, 200, 240
+    with Pool(8) as p:
+        d2 = np.array(p.map(_densities, [(2, L, M, T, i) for i in range(R)]))
+        d1 = np.array(p.map(_densities, [(1, L, M, T, i) for i in range(R)]))
+    diff = np.abs(d1.mean(0) - d2.mean(0))
+    se = np.sqrt(d1.var(0, ddof=1) / R + d2.var(0, ddof=1) / R)
+    assert (diff <= np.maximum(4 * se, 0.005)).all(), (diff, se)
