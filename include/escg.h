@@ -1,0 +1,189 @@
+/*
+ * escg.h -- C ABI of the MI355X (gfx950) ESCG Monte Carlo library.
+ *
+ * The library advances L x L periodic von Neumann lattices of uint8 species
+ * states (0 = empty, 1..S) by the elementary step of an Evolutionary Spatial
+ * Cyclic Game: a site and one of its four neighbours interact by exchange
+ * (the paper's migration), selection (interaction through the dominance
+ * matrix) or reproduction into an empty site (arxiv 2508.16639, Sec.
+ * "Single Threaded ESCG in C++": Algorithm "Elementary Step", Algorithm
+ * "Dominance Check", the circulant dominance matrix equation and the action
+ * probability normalisation).
+ *
+ * Updates run on a conflict-free schedule: one Monte Carlo step (MCS) is
+ * four passes; each pass tiles the lattice into disjoint 2x2 blocks at a
+ * random offset and updates one random internal edge per block, so one MCS
+ * is L*L elementary steps, as in the paper's Overall ESCG Loop.  All random
+ * numbers come from Philox4x32-10 (Salmon et al., SC'11) keyed by the job
+ * seed, with counters built from (site or block, MCS index, pass, replica):
+ * a result depends only on (parameters, input lattice, absolute MCS index),
+ * never on launch shape, batching, co-running jobs or how a run is split.
+ * The block words, thresholds and stream tags are defined in the library
+ * source (escg_device.hpp).
+ *
+ * Conventions for every entry point:
+ *   - Return value: ESCG_OK (0) or a negative escg_status.  Parameters are
+ *     validated on the host before anything is enqueued; on any error
+ *     nothing is enqueued and no output is touched.
+ *   - Pointers named d_* are device pointers (HIP device memory of the
+ *     current device, caller-owned, e.g. torch tensors' data_ptr()).
+ *     Pointers named h_* are host pointers read before the call returns.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *     Work is enqueued asynchronously on it; outputs are valid once the
+ *     stream has completed.  Exception: escg_run_until_extinction on a
+ *     lattice too large for one workgroup's LDS synchronises the stream
+ *     while it runs (it polls the stop flag between chunks of MCS).
+ *   - Lattices are row-major uint8[L*L], site (row, col) at row*L + col.
+ *     Every site value must be in 0..S; other values give unspecified
+ *     (but memory-safe) results.
+ *   - Calls on different streams may run concurrently, on different
+ *     lattices.  Scratch memory is stream-ordered (hipMallocAsync) and
+ *     private to each call.
+ */
+#ifndef ESCG_H
+#define ESCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t escg_status;
+#define ESCG_OK             0
+#define ESCG_EINVAL        (-1) /* invalid argument; nothing enqueued        */
+#define ESCG_ENOMEM        (-2) /* device scratch allocation failed           */
+#define ESCG_EDEVICE       (-3) /* a HIP call failed                          */
+#define ESCG_EUNSUPPORTED  (-4) /* valid request this build cannot run        */
+#define ESCG_ETIMEOUT      (-5) /* a device wait exceeded its spin bound      */
+
+#define ESCG_MAX_SPECIES   31u
+#define ESCG_MAX_L         46340u /* L*L fits in 31 bits                      */
+
+/* Stop conditions (checked on the species counts after every MCS and on the
+ * input state).  The paper stops at monoculture (its stasis check, Sec.
+ * "Metal ESCG Implementation"); the extinction workloads stop at the first
+ * extinction of any species. */
+#define ESCG_STOP_FIRST_EXTINCTION 0u /* some species 1..S has count 0       */
+#define ESCG_STOP_MONOCULTURE      1u /* at most one species 1..S remains    */
+#define ESCG_STOP_NONE             2u /* run the full MCS budget              */
+
+/* Job parameters.  Rates are named by role; only their ratios matter (the
+ * paper normalises them into a roulette).  dom[a] bit b (1 <= a, b <= S) is
+ * set iff species a dominates species b (the paper's flat matrix entry
+ * D[(a-1)*S + (b-1)]); dom[0], bit 0 and bits above S must be zero. */
+typedef struct escg_params {
+    uint32_t L;        /* lattice side, even, 2 <= L <= ESCG_MAX_L          */
+    uint32_t S;        /* species, 1 <= S <= ESCG_MAX_SPECIES               */
+    uint32_t dom[32];  /* dominance bitmasks, see above                     */
+    double   rate_ex;  /* exchange (migration) rate  >= 0, finite           */
+    double   rate_sel; /* selection (interaction) rate >= 0, finite         */
+    double   rate_rep; /* reproduction rate >= 0, finite; sum > 0           */
+    uint64_t seed;     /* Philox key                                        */
+    uint32_t replica;  /* independent stream id under the same seed         */
+    uint32_t reserved; /* must be 0                                         */
+} escg_params;
+
+/* Human-readable name of a status code (static storage). */
+const char *escg_status_str(escg_status s);
+
+/* Name and description of the last HIP error this thread's calls turned into
+ * ESCG_EDEVICE ("" if none); valid until the thread's next failing call. */
+const char *escg_last_error(void);
+
+/* Circulant dominance C(S, K) of the paper's circulant matrix equation:
+ * species i dominates j iff (j - i) mod S is in K.  kmask bit k set <=> k in
+ * K (bit 0 ignored).  Writes dom[0..31].  EINVAL if S is out of range or dom
+ * is NULL. */
+escg_status escg_circulant_dom(uint32_t S, uint32_t kmask, uint32_t *h_dom);
+
+/* Dominance bitmasks from the paper's flat S*S matrix (Algorithm "Dominance
+ * Check" layout; nonzero entry = dominates).  EINVAL on NULL or bad S. */
+escg_status escg_dom_from_matrix(uint32_t S, const uint8_t *h_D,
+                                 uint32_t *h_dom);
+
+/* The two 24-bit action thresholds of the job: an elementary step with
+ * uniform 24-bit draw u is an exchange if u < T1, a selection if
+ * T1 <= u < T2, else a reproduction, where (in IEEE double, this order)
+ * tot = (ex + sel) + rep, T1 = floor(2^24 ex / tot),
+ * T2 = floor(2^24 (ex + sel) / tot).  This is the paper's roulette
+ * (Algorithm "Elementary Step": migration first, then interaction, then
+ * reproduction) with the float draw replaced by integers.  EINVAL on bad
+ * rates or NULL. */
+escg_status escg_thresholds(const escg_params *p, uint32_t *T1, uint32_t *T2);
+
+/* Fills d_lattice (uint8[L*L]) with the initial state: every site i.i.d.
+ * uniform over {0, ..., S} (0 = empty), drawn from (seed, replica, site).
+ * The paper initialises occupied sites uniformly over species with a chosen
+ * empty probability (Sec. "Single Threaded ESCG in C++"); here that
+ * probability is 1/(S+1). */
+escg_status escg_init(const escg_params *p, uint8_t *d_lattice, void *stream);
+
+/* Species counts of d_lattice: d_counts (uint32[S+1]) receives, for
+ * v = 0..S, the number of sites equal to v (the paper's densities() before
+ * division by L*L, Algorithm "Overall ESCG Loop"). */
+escg_status escg_densities(const escg_params *p, const uint8_t *d_lattice,
+                           uint32_t *d_counts, void *stream);
+
+/* Advances d_lattice in place by n_mcs Monte Carlo steps whose absolute
+ * indices are mcs0 .. mcs0 + n_mcs - 1 (the index keys the random streams,
+ * so splitting a run into several calls gives the same bytes).  If d_counts
+ * is non-NULL it receives uint32[(n_mcs + 1) * (S + 1)]: row k holds the
+ * species counts after k of these MCS, row 0 those of the input (the
+ * paper's per-MCS density record).  n_mcs = 0 only writes row 0. */
+escg_status escg_step_mcs(const escg_params *p, uint8_t *d_lattice,
+                          uint32_t mcs0, uint32_t n_mcs, uint32_t *d_counts,
+                          void *stream);
+
+/* Runs from absolute MCS mcs0 until the stop condition `mode` holds or
+ * max_mcs MCS have been done.  d_result (uint32[S + 3]) receives
+ * {flag, t_ext, counts[0..S]}: flag = 1 if the condition held after t_ext
+ * MCS of this call (t_ext = 0: the input already met it), else flag = 0 and
+ * t_ext = max_mcs; counts are those of the returned lattice, which is the
+ * state at t_ext.  The paper's loop stops at monoculture (stasis());
+ * ESCG_STOP_NONE runs all max_mcs MCS. */
+escg_status escg_run_until_extinction(const escg_params *p, uint8_t *d_lattice,
+                                      uint32_t mcs0, uint32_t max_mcs,
+                                      uint32_t mode, uint32_t *d_result,
+                                      void *stream);
+
+/* Largest L that escg_batch_run accepts (the whole lattice must fit one
+ * workgroup's LDS). */
+uint32_t escg_batch_max_L(void);
+
+/* Many independent jobs in one launch of a persistent kernel: each
+ * workgroup takes jobs from a queue (longest first), keeps the job's
+ * lattice in LDS for its whole run, and writes it back at the end.
+ *   h_params[n]      job parameters (L <= escg_batch_max_L())
+ *   h_offsets[n]     byte offset of job j's lattice inside d_lattices;
+ *                    lattices must not overlap
+ *   h_mcs0[n]        absolute MCS index each job starts at (NULL = all 0)
+ *   h_max_mcs[n]     MCS budget per job
+ *   mode             stop condition (ESCG_STOP_*), as in
+ *                    escg_run_until_extinction
+ *   init             nonzero: the lattice is first initialised as by
+ *                    escg_init (then mcs0 is still honoured); zero: the
+ *                    lattice in d_lattices is the input state
+ *   d_results        uint32[n * 34]: job j's {flag, t_ext, counts[0..S]}
+ *                    at d_results + 34 j (unused tail words are zeroed)
+ * Every job's output equals escg_run_until_extinction on the same job
+ * alone, byte for byte. */
+#define ESCG_BATCH_RESULT_WORDS 34u
+escg_status escg_batch_run(uint32_t n, const escg_params *h_params,
+                           const uint64_t *h_offsets, uint8_t *d_lattices,
+                           const uint32_t *h_mcs0, const uint32_t *h_max_mcs,
+                           uint32_t mode, uint32_t init, uint32_t *d_results,
+                           void *stream);
+
+/* Single-job routing knob: escg_step_mcs keeps a lattice with
+ * L <= min(L_max, escg_batch_max_L()) whole in one workgroup's LDS and sends
+ * larger ones to the tiled all-CU path (default 192).  Both paths produce
+ * the same bytes; the knob only trades latency for occupancy.  Process-wide;
+ * always ESCG_OK. */
+escg_status escg_set_single_lds_max_L(uint32_t L_max);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ESCG_H */

@@ -1,0 +1,1046 @@
+// escg.hip -- HIP kernels (gfx950) and the C ABI of the ESCG hot path.
+//
+// Kernels
+//   init_kernel        counter-RNG initial lattice, one Philox call per
+//                      4 sites, dword stores
+//   densities_kernel   species counts: per-lane SWAR byte compares, wave
+//                      reduction, one atomic per workgroup and species
+//   lds_*_kernel       whole lattice resident in LDS for the entire run
+//                      (L <= 404): four block passes per MCS separated by
+//                      workgroup barriers, counts and the stop test after
+//                      every MCS, one workgroup per job; the batch variant is
+//                      persistent and pulls jobs from a queue
+//   tile_mcs_kernel    large lattices: one launch per MCS, each workgroup
+//                      stages a tile plus a 4-row / 8-column halo in LDS,
+//                      runs the four passes there (a 4-site halo covers the
+//                      four passes' dependency cone), counts its interior and
+//                      writes it to the other buffer of a ping-pong pair
+//
+// See escg_device.hpp for the schedule / random-number contract.
+#include "escg_device.hpp"
+#include "escg.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+using namespace escg;
+
+namespace {
+
+constexpr uint32_t kLdsHeader = 512;    // dom table, counts, misc words
+constexpr uint32_t kResultWords = ESCG_BATCH_RESULT_WORDS;
+
+// ---------------------------------------------------------------------------
+// Job descriptor of the LDS-resident kernels
+// ---------------------------------------------------------------------------
+struct JobDev {
+    uint64_t seed;
+    uint64_t lat_off;     // byte offset of the lattice in the base pointer
+    uint64_t dom_packed;  // DomPacked bits (S <= 7)
+    uint32_t *counts;     // optional per-MCS count rows (max_mcs+1)*(S+1)
+    uint32_t *result;     // optional {flag, t_ext, counts[0..S]}
+    uint32_t L, S, T1, T2;
+    uint32_t replica, mcs0, max_mcs, mode;
+    uint32_t init, result_words, pad0, pad1;
+    uint32_t dom[32];
+};
+
+__device__ __forceinline__ bool stop_met(const uint32_t *c, uint32_t S,
+                                         uint32_t mode)
+{
+    if (mode == ESCG_STOP_NONE)
+        return false;
+    uint32_t alive = 0;
+    for (uint32_t s = 1; s <= S; ++s)
+        alive += c[s] > 0u;
+    return mode == ESCG_STOP_FIRST_EXTINCTION ? alive < S : alive <= 1u;
+}
+
+// Counts sites of value 0..S among ndw dwords of LDS; adds into cnt[0..S]
+// (LDS, zeroed beforehand).
+template <int SM>
+__device__ __forceinline__ void count_dwords(const uint32_t *lat32,
+                                             uint32_t ndw, uint32_t S,
+                                             uint32_t *cnt)
+{
+    uint32_t ne[SM];
+#pragma unroll
+    for (int s = 0; s < SM; ++s)
+        ne[s] = 0;
+    uint32_t mine = 0;
+    for (uint32_t i = threadIdx.x; i < ndw; i += blockDim.x) {
+        const uint32_t v = lat32[i];
+        ++mine;
+#pragma unroll
+        for (int s = 0; s < SM; ++s)
+            if ((uint32_t)s <= S)
+                ne[s] += bytes_ne(v, (uint32_t)s);
+    }
+#pragma unroll
+    for (int s = 0; s < SM; ++s) {
+        if ((uint32_t)s <= S) {
+            const uint32_t c = wave_sum(4u * mine - ne[s]);
+            if ((threadIdx.x & 63u) == 0 && c)
+                atomicAdd(&cnt[s], c);
+        }
+    }
+}
+
+// One MCS (four passes) on an L x L lattice held whole in LDS.
+template <class Dom>
+__device__ __forceinline__ void lds_mcs(uint8_t *lat, const JobDev &J,
+                                        uint32_t t, uint32_t k0, uint32_t k1,
+                                        const Dom &dom, uint32_t by0,
+                                        uint32_t qx0, uint32_t dby,
+                                        uint32_t dqx)
+{
+    const uint32_t L = J.L, Lb = L >> 1, Q = (Lb + 3) >> 2, nq = Lb * Q;
+    const Words off = philox10(0u, t, kTagOffset << 8, J.replica, k0, k1);
+#pragma unroll
+    for (uint32_t p = 0; p < 4; ++p) {
+        const uint32_t ox = off.w[p] & 1u, oy = (off.w[p] >> 1) & 1u;
+        uint32_t by = by0, qx = qx0;
+        for (uint32_t qi = threadIdx.x; qi < nq; qi += blockDim.x) {
+            const Words r = philox10(qi, t, (kTagPass << 8) | p, J.replica,
+                                     k0, k1);
+            const uint32_t r0 = 2u * by + oy;
+            const uint32_t r1 = (r0 + 1u == L) ? 0u : r0 + 1u;
+            const uint32_t rowA = r0 * L, rowC = r1 * L;
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) {
+                const uint32_t bx = 4u * qx + j;
+                if (bx < Lb) {
+                    const uint32_t c0 = 2u * bx + ox;
+                    const uint32_t c1 = (c0 + 1u == L) ? 0u : c0 + 1u;
+                    update_block(lat, rowA + c0, rowA + c1, rowC + c0,
+                                 rowC + c1, r.w[j], J.T1, J.T2, dom);
+                }
+            }
+            qx += dqx;
+            by += dby;
+            if (qx >= Q) {
+                qx -= Q;
+                ++by;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <bool kPacked>
+__device__ void run_job_lds(const JobDev &J, uint8_t *base, uint8_t *smem)
+{
+    uint32_t *s_dom = reinterpret_cast<uint32_t *>(smem);
+    uint32_t *s_cnt = s_dom + 32; // two rows of 32
+    uint8_t *lat = smem + kLdsHeader;
+    uint32_t *lat32 = reinterpret_cast<uint32_t *>(lat);
+    const uint32_t tid = threadIdx.x, nt = blockDim.x;
+    const uint32_t L = J.L, S = J.S, N = L * L, ndw = N >> 2;
+    const uint32_t k0 = (uint32_t)J.seed, k1 = (uint32_t)(J.seed >> 32);
+    uint8_t *g = base + J.lat_off;
+    uint32_t *g32 = reinterpret_cast<uint32_t *>(g);
+
+    if (tid < 32)
+        s_dom[tid] = J.dom[tid];
+    if (tid < 64)
+        s_cnt[tid] = 0;
+    if (J.init) {
+        for (uint32_t i = tid; i < ndw; i += nt) {
+            const Words w = philox10(i, 0u, kTagInit << 8, J.replica, k0, k1);
+            uint32_t v = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                v |= (uint32_t)(((uint64_t)w.w[j] * (S + 1u)) >> 32) << (8 * j);
+            lat32[i] = v;
+        }
+    } else {
+        for (uint32_t i = tid; i < ndw; i += nt)
+            lat32[i] = g32[i];
+    }
+    __syncthreads();
+
+    DomPacked dp{J.dom_packed};
+    DomTable dt{s_dom};
+    const uint32_t Lb = L >> 1, Q = (Lb + 3) >> 2;
+    const uint32_t by0 = tid / Q, qx0 = tid - by0 * Q;
+    const uint32_t dby = nt / Q, dqx = nt - dby * Q;
+
+    uint32_t cur = 0;
+    if (kPacked)
+        count_dwords<8>(lat32, ndw, S, s_cnt);
+    else
+        count_dwords<32>(lat32, ndw, S, s_cnt);
+    __syncthreads();
+    bool stop = stop_met(s_cnt, S, J.mode);
+    if (J.counts && tid <= S)
+        J.counts[tid] = s_cnt[tid];
+    uint32_t t = 0;
+    while (!stop && t < J.max_mcs) {
+        const uint32_t nxt = cur ^ 1u;
+        if (tid < 32)
+            s_cnt[nxt * 32 + tid] = 0;
+        if (kPacked)
+            lds_mcs(lat, J, J.mcs0 + t, k0, k1, dp, by0, qx0, dby, dqx);
+        else
+            lds_mcs(lat, J, J.mcs0 + t, k0, k1, dt, by0, qx0, dby, dqx);
+        if (kPacked)
+            count_dwords<8>(lat32, ndw, S, s_cnt + nxt * 32);
+        else
+            count_dwords<32>(lat32, ndw, S, s_cnt + nxt * 32);
+        __syncthreads();
+        cur = nxt;
+        ++t;
+        stop = stop_met(s_cnt + cur * 32, S, J.mode);
+        if (J.counts && tid <= S)
+            J.counts[(size_t)t * (S + 1) + tid] = s_cnt[cur * 32 + tid];
+    }
+    for (uint32_t i = tid; i < ndw; i += nt)
+        g32[i] = lat32[i];
+    if (J.result) {
+        for (uint32_t i = tid; i < J.result_words; i += nt) {
+            uint32_t v = 0;
+            if (i == 0)
+                v = stop ? 1u : 0u;
+            else if (i == 1)
+                v = t;
+            else if (i - 2 <= S)
+                v = s_cnt[cur * 32 + (i - 2)];
+            J.result[i] = v;
+        }
+    }
+    __syncthreads();
+}
+
+template <bool kPacked>
+__global__ __launch_bounds__(512) void lds_single_kernel(JobDev J,
+                                                         uint8_t *base)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    run_job_lds<kPacked>(J, base, smem);
+}
+
+template <bool kPacked>
+__global__ __launch_bounds__(512) void lds_batch_kernel(
+    const JobDev *__restrict__ jobs, const uint32_t *__restrict__ order,
+    uint32_t n, uint32_t *queue, uint8_t *base)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ uint32_t s_next;
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_next = atomicAdd(queue, 1u);
+        __syncthreads();
+        const uint32_t qi = s_next;
+        __syncthreads();
+        if (qi >= n)
+            return;
+        run_job_lds<kPacked>(jobs[order[qi]], base, smem);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Large lattices: one launch per MCS over tiles with halos
+// ---------------------------------------------------------------------------
+constexpr int kTileH = 64;
+constexpr int kTileW = 128;
+constexpr int kHaloR = 4;
+constexpr int kHaloC = 8;
+constexpr int kTileThreads = 256;
+
+struct TileArgs {
+    const uint8_t *src;
+    uint8_t *dst;
+    uint32_t *counts;     // S+1 words of this MCS's row (zeroed) or null
+    const uint32_t *done; // non-null and nonzero: only copy src to dst
+    uint64_t seed;
+    uint64_t dom_packed;
+    uint32_t L, S, T1, T2, replica, t;
+    uint32_t dom[32];
+};
+
+template <bool kPacked>
+__global__ __launch_bounds__(kTileThreads) void tile_mcs_kernel(TileArgs a)
+{
+    constexpr uint32_t LS = kTileW + 2 * kHaloC; // LDS row stride
+    constexpr uint32_t RH = kTileH + 2 * kHaloR;
+    __shared__ __align__(16) uint8_t lat[RH * LS];
+    __shared__ uint32_t s_dom[32];
+    __shared__ uint32_t s_cnt[32];
+    const uint32_t tid = threadIdx.x, nt = blockDim.x;
+    const uint32_t L = a.L, S = a.S, Lb = L >> 1, Q = (Lb + 3) >> 2;
+    const uint32_t R0 = blockIdx.y * kTileH, g0 = blockIdx.x * kTileW;
+    const uint32_t th = min((uint32_t)kTileH, L - R0);
+    const uint32_t tw = min((uint32_t)kTileW, L - g0);
+    const bool aligned = (L & 3u) == 0;
+
+    if (a.done && *a.done) { // stopped: carry the state over unchanged
+        for (uint32_t i = tid; i < th * tw; i += nt) {
+            const uint32_t r = i / tw, c = i - r * tw;
+            const size_t gi = (size_t)(R0 + r) * L + g0 + c;
+            a.dst[gi] = a.src[gi];
+        }
+        return;
+    }
+    if (tid < 32) {
+        s_dom[tid] = a.dom[tid];
+        s_cnt[tid] = 0;
+    }
+    // Stage rows R0-4 .. R0+th+4 and columns g0-8 .. g0+tw+8 (mod L).
+    {
+        const uint32_t rows = th + 2 * kHaloR, dwr = (tw + 2 * kHaloC) >> 2;
+        for (uint32_t i = tid; i < rows * dwr; i += nt) {
+            const uint32_t lr = i / dwr, j = i - lr * dwr;
+            const uint32_t gr = (R0 + L - kHaloR + lr) % L;
+            const uint32_t gc = (g0 + L - kHaloC + 4 * j) % L;
+            uint32_t v;
+            if (aligned) {
+                v = *reinterpret_cast<const uint32_t *>(a.src + (size_t)gr * L +
+                                                        gc);
+            } else {
+                v = 0;
+                for (uint32_t b = 0; b < 4; ++b) {
+                    const uint32_t c = (gc + b) % L;
+                    v |= (uint32_t)a.src[(size_t)gr * L + c] << (8 * b);
+                }
+            }
+            *reinterpret_cast<uint32_t *>(&lat[lr * LS + 4 * j]) = v;
+        }
+    }
+    __syncthreads();
+
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    DomPacked dp{a.dom_packed};
+    DomTable dt{s_dom};
+    const Words off = philox10(0u, a.t, kTagOffset << 8, a.replica, k0, k1);
+    const int bx_base = (int)(g0 >> 1) - kHaloC / 2; // global bx of m = 0
+#pragma unroll
+    for (uint32_t p = 0; p < 4; ++p) {
+        const uint32_t ox = off.w[p] & 1u, oy = (off.w[p] >> 1) & 1u;
+        const uint32_t nbr = (th + 2 * kHaloR - oy) >> 1;
+        const uint32_t nbc = (tw + 2 * kHaloC - ox) >> 1;
+        const uint32_t nqs = (nbc + 3) >> 2;
+        const uint32_t ctr2 = (kTagPass << 8) | p;
+        for (uint32_t i = tid; i < nbr * nqs; i += nt) {
+            const uint32_t k = i / nqs, js = i - k * nqs;
+            const uint32_t lr = oy + 2 * k;
+            const uint32_t gr = (R0 + L - kHaloR + lr) % L;
+            const uint32_t by = (gr - oy) >> 1;
+            const uint32_t m0 = 4 * js;
+            const uint32_t mlast = min(m0 + 3, nbc - 1);
+            int bxf = bx_base + (int)m0, bxl = bx_base + (int)mlast;
+            bxf += bxf < 0 ? (int)Lb : 0;
+            bxf -= bxf >= (int)Lb ? (int)Lb : 0;
+            bxl += bxl < 0 ? (int)Lb : 0;
+            bxl -= bxl >= (int)Lb ? (int)Lb : 0;
+            const uint32_t qf = (uint32_t)bxf >> 2, ql = (uint32_t)bxl >> 2;
+            const Words rf = philox10(by * Q + qf, a.t, ctr2, a.replica, k0, k1);
+            Words rl = rf;
+            if (ql != qf)
+                rl = philox10(by * Q + ql, a.t, ctr2, a.replica, k0, k1);
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) {
+                const uint32_t m = m0 + j;
+                const uint32_t lc = ox + 2 * m;
+                if (m < nbc && lc >= (uint32_t)(kHaloC - kHaloR) &&
+                    lc + 1 < tw + kHaloC + kHaloR) {
+                    int bx = bx_base + (int)m;
+                    bx += bx < 0 ? (int)Lb : 0;
+                    bx -= bx >= (int)Lb ? (int)Lb : 0;
+                    const uint32_t q = (uint32_t)bx >> 2;
+                    const uint32_t w = pick(q == qf ? rf : rl, (uint32_t)bx & 3u);
+                    const uint32_t pA = lr * LS + lc;
+                    if (kPacked)
+                        update_block(lat, pA, pA + 1, pA + LS, pA + LS + 1, w,
+                                     a.T1, a.T2, dp);
+                    else
+                        update_block(lat, pA, pA + 1, pA + LS, pA + LS + 1, w,
+                                     a.T1, a.T2, dt);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // Interior: LDS rows 4 .. th+4, columns 8 .. tw+8.
+    uint32_t ne[kPacked ? 8 : 32];
+    constexpr int SM = kPacked ? 8 : 32;
+#pragma unroll
+    for (int s = 0; s < SM; ++s)
+        ne[s] = 0;
+    uint32_t mine = 0;
+    if (aligned && (tw & 3u) == 0) {
+        const uint32_t dwr = tw >> 2;
+        for (uint32_t i = tid; i < th * dwr; i += nt) {
+            const uint32_t r = i / dwr, j = i - r * dwr;
+            const uint32_t v = *reinterpret_cast<const uint32_t *>(
+                &lat[(r + kHaloR) * LS + kHaloC + 4 * j]);
+            *reinterpret_cast<uint32_t *>(a.dst + (size_t)(R0 + r) * L + g0 +
+                                          4 * j) = v;
+            ++mine;
+#pragma unroll
+            for (int s = 0; s < SM; ++s)
+                if ((uint32_t)s <= S)
+                    ne[s] += bytes_ne(v, (uint32_t)s);
+        }
+        mine *= 4;
+    } else {
+        for (uint32_t i = tid; i < th * tw; i += nt) {
+            const uint32_t r = i / tw, c = i - r * tw;
+            const uint32_t v = lat[(r + kHaloR) * LS + kHaloC + c];
+            a.dst[(size_t)(R0 + r) * L + g0 + c] = (uint8_t)v;
+            ++mine;
+#pragma unroll
+            for (int s = 0; s < SM; ++s)
+                if ((uint32_t)s <= S)
+                    ne[s] += (v != (uint32_t)s) ? 1u : 0u;
+        }
+    }
+    if (a.counts) {
+#pragma unroll
+        for (int s = 0; s < SM; ++s) {
+            if ((uint32_t)s <= S) {
+                const uint32_t c = wave_sum(mine - ne[s]);
+                if ((tid & 63u) == 0 && c)
+                    atomicAdd(&s_cnt[s], c);
+            }
+        }
+        __syncthreads();
+        if (tid <= S && s_cnt[tid])
+            atomicAdd(&a.counts[tid], s_cnt[tid]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Small kernels
+// ---------------------------------------------------------------------------
+__global__ void init_kernel(uint32_t *lat32, uint32_t ndw, uint32_t S,
+                            uint64_t seed, uint32_t replica)
+{
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ndw;
+         i += gridDim.x * blockDim.x) {
+        const Words w = philox10(i, 0u, kTagInit << 8, replica, k0, k1);
+        uint32_t v = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            v |= (uint32_t)(((uint64_t)w.w[j] * (S + 1u)) >> 32) << (8 * j);
+        lat32[i] = v;
+    }
+}
+
+template <int SM>
+__global__ __launch_bounds__(256) void densities_kernel(const uint32_t *lat32,
+                                                        uint32_t ndw,
+                                                        uint32_t S,
+                                                        uint32_t *counts)
+{
+    __shared__ uint32_t s_cnt[32];
+    if (threadIdx.x < 32)
+        s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t ne[SM];
+#pragma unroll
+    for (int s = 0; s < SM; ++s)
+        ne[s] = 0;
+    uint32_t mine = 0;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ndw;
+         i += gridDim.x * blockDim.x) {
+        const uint32_t v = lat32[i];
+        ++mine;
+#pragma unroll
+        for (int s = 0; s < SM; ++s)
+            if ((uint32_t)s <= S)
+                ne[s] += bytes_ne(v, (uint32_t)s);
+    }
+#pragma unroll
+    for (int s = 0; s < SM; ++s) {
+        if ((uint32_t)s <= S) {
+            const uint32_t c = wave_sum(4u * mine - ne[s]);
+            if ((threadIdx.x & 63u) == 0 && c)
+                atomicAdd(&s_cnt[s], c);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x <= S && s_cnt[threadIdx.x])
+        atomicAdd(&counts[threadIdx.x], s_cnt[threadIdx.x]);
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, size_t n, uint32_t v)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void copy_u32_kernel(uint32_t *dst, const uint32_t *src, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// Stop test between tile MCS launches.  st = {done, flag, t_ext}; cnt2 holds
+// two rows of 32 counts, row `row` is the state after t_after MCS; the other
+// row is cleared for the next MCS.
+__global__ void check_stop_kernel(uint32_t *st, uint32_t *cnt2, uint32_t row,
+                                  uint32_t S, uint32_t mode, uint32_t t_after,
+                                  uint32_t *result)
+{
+    if (threadIdx.x != 0)
+        return;
+    const uint32_t *c = cnt2 + row * 32;
+    if (!st[0]) {
+        const bool met = stop_met(c, S, mode);
+        for (uint32_t s = 0; s <= S; ++s)
+            result[2 + s] = c[s];
+        result[0] = met ? 1u : 0u;
+        result[1] = t_after;
+        if (met)
+            st[0] = 1u;
+    }
+    for (uint32_t s = 0; s < 32; ++s)
+        cnt2[(row ^ 1u) * 32 + s] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+struct Derived {
+    uint32_t T1, T2;
+    uint64_t packed;
+    bool small; // S <= 7: packed dominance
+};
+
+escg_status validate(const escg_params *p)
+{
+    if (!p)
+        return ESCG_EINVAL;
+    if (p->L < 2 || (p->L & 1u) || p->L > ESCG_MAX_L)
+        return ESCG_EINVAL;
+    if (p->S < 1 || p->S > ESCG_MAX_SPECIES)
+        return ESCG_EINVAL;
+    if (p->reserved != 0)
+        return ESCG_EINVAL;
+    const double r[3] = {p->rate_ex, p->rate_sel, p->rate_rep};
+    for (double v : r)
+        if (!(v >= 0.0) || !std::isfinite(v))
+            return ESCG_EINVAL;
+    if (!((p->rate_ex + p->rate_sel) + p->rate_rep > 0.0))
+        return ESCG_EINVAL;
+    if (p->dom[0] != 0)
+        return ESCG_EINVAL;
+    const uint32_t valid = (p->S >= 31 ? 0xFFFFFFFFu : ((2u << p->S) - 1u)) &
+                           ~1u;
+    for (uint32_t a = 1; a < 32; ++a) {
+        if (a > p->S && p->dom[a] != 0)
+            return ESCG_EINVAL;
+        if (p->dom[a] & ~valid)
+            return ESCG_EINVAL;
+    }
+    return ESCG_OK;
+}
+
+Derived derive(const escg_params *p)
+{
+    Derived d;
+    escg_thresholds(p, &d.T1, &d.T2);
+    d.small = p->S <= 7;
+    d.packed = 0;
+    if (d.small)
+        for (uint32_t a = 1; a <= p->S; ++a)
+            for (uint32_t b = 1; b <= p->S; ++b)
+                if ((p->dom[a] >> b) & 1u)
+                    d.packed |= 1ull << (a * 8 + b);
+    return d;
+}
+
+inline hipStream_t S_(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+struct DeviceInfo {
+    int cus = 0;
+    size_t lds_max = 0;
+};
+
+DeviceInfo device_info()
+{
+    static std::mutex mu;
+    static std::vector<DeviceInfo> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return DeviceInfo{};
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)cache.size() <= dev)
+        cache.resize(dev + 1);
+    if (cache[dev].cus == 0) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            cache[dev].cus = prop.multiProcessorCount;
+            cache[dev].lds_max = prop.sharedMemPerBlock;
+        }
+    }
+    return cache[dev];
+}
+
+uint32_t lds_max_L()
+{
+    const DeviceInfo di = device_info();
+    size_t lds = di.lds_max ? di.lds_max : 65536;
+    const size_t reserve = kLdsHeader + 64; // + static LDS of the kernels
+    if (lds <= reserve)
+        return 0;
+    uint32_t L = (uint32_t)std::floor(std::sqrt((double)(lds - reserve)));
+    L &= ~1u;
+    while (L > 0 && (size_t)L * L + reserve > lds)
+        L -= 2;
+    return L;
+}
+
+// Single jobs run in the LDS-resident kernel up to this L (one workgroup, so
+// larger single lattices go to the tiled multi-workgroup path).
+std::atomic<uint32_t> g_single_lds_max_L{192};
+
+thread_local char g_last_error[160] = "";
+
+escg_status last_hip(hipError_t e)
+{
+    if (e == hipSuccess)
+        return ESCG_OK;
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s",
+                  hipGetErrorName(e), hipGetErrorString(e));
+    return ESCG_EDEVICE;
+}
+
+// Raises the dynamic-LDS limit of a kernel when the runtime supports it; a
+// refusal is not an error by itself (the launch reports real failures), so
+// the sticky error it leaves is cleared.
+void allow_dynamic_lds(const void *fn, size_t bytes)
+{
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)bytes) != hipSuccess)
+        (void)hipGetLastError();
+}
+
+JobDev make_job(const escg_params *p, const Derived &d, uint64_t off,
+                uint32_t mcs0, uint32_t max_mcs, uint32_t mode, uint32_t init,
+                uint32_t *counts, uint32_t *result, uint32_t result_words)
+{
+    JobDev J;
+    std::memset(&J, 0, sizeof(J));
+    J.seed = p->seed;
+    J.lat_off = off;
+    J.dom_packed = d.packed;
+    J.counts = counts;
+    J.result = result;
+    J.L = p->L;
+    J.S = p->S;
+    J.T1 = d.T1;
+    J.T2 = d.T2;
+    J.replica = p->replica;
+    J.mcs0 = mcs0;
+    J.max_mcs = max_mcs;
+    J.mode = mode;
+    J.init = init;
+    J.result_words = result_words;
+    for (int i = 0; i < 32; ++i)
+        J.dom[i] = p->dom[i];
+    return J;
+}
+
+uint32_t lds_threads(uint32_t Lmax) { return Lmax <= 128 ? 256u : 512u; }
+
+escg_status launch_lds_single(const JobDev &J, bool small, uint8_t *base,
+                              hipStream_t st)
+{
+    const size_t lds = kLdsHeader + (size_t)J.L * J.L;
+    const uint32_t nt = lds_threads(J.L);
+    if (small) {
+        allow_dynamic_lds((const void *)lds_single_kernel<true>, lds);
+        hipLaunchKernelGGL(lds_single_kernel<true>, dim3(1), dim3(nt), lds, st,
+                           J, base);
+    } else {
+        allow_dynamic_lds((const void *)lds_single_kernel<false>, lds);
+        hipLaunchKernelGGL(lds_single_kernel<false>, dim3(1), dim3(nt), lds,
+                           st, J, base);
+    }
+    return last_hip(hipGetLastError());
+}
+
+escg_status launch_densities(const uint8_t *lat, uint32_t N, uint32_t S,
+                             uint32_t *counts, hipStream_t st)
+{
+    const uint32_t ndw = N >> 2;
+    const uint32_t blocks = std::max(1u, std::min(2048u, (ndw + 255) / 256));
+    const uint32_t *l32 = reinterpret_cast<const uint32_t *>(lat);
+    if (S <= 7)
+        hipLaunchKernelGGL(densities_kernel<8>, dim3(blocks), dim3(256), 0, st,
+                           l32, ndw, S, counts);
+    else
+        hipLaunchKernelGGL(densities_kernel<32>, dim3(blocks), dim3(256), 0,
+                           st, l32, ndw, S, counts);
+    return last_hip(hipGetLastError());
+}
+
+void launch_fill(uint32_t *p, size_t n, uint32_t v, hipStream_t st)
+{
+    const uint32_t blocks =
+        (uint32_t)std::max<size_t>(1, std::min<size_t>(1024, (n + 255) / 256));
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks), dim3(256), 0, st, p, n,
+                       v);
+}
+
+void launch_copy(uint8_t *dst, const uint8_t *src, size_t bytes,
+                 hipStream_t st)
+{
+    const size_t n = bytes >> 2;
+    const uint32_t blocks =
+        (uint32_t)std::max<size_t>(1, std::min<size_t>(4096, (n + 255) / 256));
+    hipLaunchKernelGGL(copy_u32_kernel, dim3(blocks), dim3(256), 0, st,
+                       reinterpret_cast<uint32_t *>(dst),
+                       reinterpret_cast<const uint32_t *>(src), n);
+}
+
+TileArgs tile_args(const escg_params *p, const Derived &d)
+{
+    TileArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.seed = p->seed;
+    a.dom_packed = d.packed;
+    a.L = p->L;
+    a.S = p->S;
+    a.T1 = d.T1;
+    a.T2 = d.T2;
+    a.replica = p->replica;
+    for (int i = 0; i < 32; ++i)
+        a.dom[i] = p->dom[i];
+    return a;
+}
+
+void launch_tile_mcs(const TileArgs &a, bool small, hipStream_t st)
+{
+    const dim3 grid((a.L + kTileW - 1) / kTileW, (a.L + kTileH - 1) / kTileH);
+    if (small)
+        hipLaunchKernelGGL(tile_mcs_kernel<true>, grid, dim3(kTileThreads), 0,
+                           st, a);
+    else
+        hipLaunchKernelGGL(tile_mcs_kernel<false>, grid, dim3(kTileThreads), 0,
+                           st, a);
+}
+
+bool aligned4(const void *p) { return ((uintptr_t)p & 3u) == 0; }
+
+} // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *escg_last_error(void) { return g_last_error; }
+
+const char *escg_status_str(escg_status s)
+{
+    switch (s) {
+    case ESCG_OK: return "ok";
+    case ESCG_EINVAL: return "invalid argument";
+    case ESCG_ENOMEM: return "device allocation failed";
+    case ESCG_EDEVICE: return "HIP runtime error";
+    case ESCG_EUNSUPPORTED: return "unsupported request";
+    case ESCG_ETIMEOUT: return "device wait timed out";
+    default: return "unknown status";
+    }
+}
+
+escg_status escg_circulant_dom(uint32_t S, uint32_t kmask, uint32_t *h_dom)
+{
+    if (!h_dom || S < 1 || S > ESCG_MAX_SPECIES)
+        return ESCG_EINVAL;
+    for (int i = 0; i < 32; ++i)
+        h_dom[i] = 0;
+    for (uint32_t i = 1; i <= S; ++i)
+        for (uint32_t j = 1; j <= S; ++j) {
+            const uint32_t k = (j + S - i) % S;
+            if (k != 0 && ((kmask >> k) & 1u))
+                h_dom[i] |= 1u << j;
+        }
+    return ESCG_OK;
+}
+
+escg_status escg_dom_from_matrix(uint32_t S, const uint8_t *h_D,
+                                 uint32_t *h_dom)
+{
+    if (!h_dom || !h_D || S < 1 || S > ESCG_MAX_SPECIES)
+        return ESCG_EINVAL;
+    for (int i = 0; i < 32; ++i)
+        h_dom[i] = 0;
+    for (uint32_t i = 1; i <= S; ++i)
+        for (uint32_t j = 1; j <= S; ++j)
+            if (h_D[(i - 1) * S + (j - 1)])
+                h_dom[i] |= 1u << j;
+    return ESCG_OK;
+}
+
+escg_status escg_thresholds(const escg_params *p, uint32_t *T1, uint32_t *T2)
+{
+    if (!p || !T1 || !T2)
+        return ESCG_EINVAL;
+    const double ex = p->rate_ex, sel = p->rate_sel, rep = p->rate_rep;
+    if (!(ex >= 0 && sel >= 0 && rep >= 0) || !std::isfinite(ex) ||
+        !std::isfinite(sel) || !std::isfinite(rep))
+        return ESCG_EINVAL;
+    const double tot = (ex + sel) + rep;
+    if (!(tot > 0))
+        return ESCG_EINVAL;
+    *T1 = (uint32_t)std::floor(std::ldexp(ex / tot, 24));
+    *T2 = (uint32_t)std::floor(std::ldexp((ex + sel) / tot, 24));
+    return ESCG_OK;
+}
+
+escg_status escg_init(const escg_params *p, uint8_t *d_lattice, void *stream)
+{
+    escg_status s = validate(p);
+    if (s != ESCG_OK)
+        return s;
+    if (!d_lattice || !aligned4(d_lattice))
+        return ESCG_EINVAL;
+    const uint32_t ndw = (uint32_t)(((uint64_t)p->L * p->L) >> 2);
+    const uint32_t blocks = std::max(1u, std::min(8192u, (ndw + 255) / 256));
+    hipLaunchKernelGGL(init_kernel, dim3(blocks), dim3(256), 0, S_(stream),
+                       reinterpret_cast<uint32_t *>(d_lattice), ndw, p->S,
+                       p->seed, p->replica);
+    return last_hip(hipGetLastError());
+}
+
+escg_status escg_densities(const escg_params *p, const uint8_t *d_lattice,
+                           uint32_t *d_counts, void *stream)
+{
+    escg_status s = validate(p);
+    if (s != ESCG_OK)
+        return s;
+    if (!d_lattice || !d_counts || !aligned4(d_lattice))
+        return ESCG_EINVAL;
+    hipStream_t st = S_(stream);
+    launch_fill(d_counts, p->S + 1, 0, st);
+    return launch_densities(d_lattice, p->L * p->L, p->S, d_counts, st);
+}
+
+escg_status escg_step_mcs(const escg_params *p, uint8_t *d_lattice,
+                          uint32_t mcs0, uint32_t n_mcs, uint32_t *d_counts,
+                          void *stream)
+{
+    escg_status s = validate(p);
+    if (s != ESCG_OK)
+        return s;
+    if (!d_lattice || !aligned4(d_lattice))
+        return ESCG_EINVAL;
+    hipStream_t st = S_(stream);
+    const Derived d = derive(p);
+    const uint32_t L = p->L, S = p->S, N = L * L;
+    if (L <= std::min(g_single_lds_max_L.load(), lds_max_L())) {
+        JobDev J = make_job(p, d, 0, mcs0, n_mcs, ESCG_STOP_NONE, 0, d_counts,
+                            nullptr, 0);
+        return launch_lds_single(J, d.small, d_lattice, st);
+    }
+    if (d_counts) {
+        launch_fill(d_counts, (size_t)(n_mcs + 1) * (S + 1), 0, st);
+        s = launch_densities(d_lattice, N, S, d_counts, st);
+        if (s != ESCG_OK)
+            return s;
+    }
+    if (n_mcs == 0)
+        return ESCG_OK;
+    uint8_t *other = nullptr;
+    if (hipMallocAsync((void **)&other, N, st) != hipSuccess)
+        return ESCG_ENOMEM;
+    TileArgs a = tile_args(p, d);
+    uint8_t *cur = d_lattice, *nxt = other;
+    for (uint32_t k = 0; k < n_mcs; ++k) {
+        a.src = cur;
+        a.dst = nxt;
+        a.t = mcs0 + k;
+        a.counts = d_counts ? d_counts + (size_t)(k + 1) * (S + 1) : nullptr;
+        launch_tile_mcs(a, d.small, st);
+        std::swap(cur, nxt);
+    }
+    if (cur != d_lattice)
+        launch_copy(d_lattice, cur, N, st);
+    s = last_hip(hipGetLastError());
+    (void)hipFreeAsync(other, st);
+    return s;
+}
+
+escg_status escg_run_until_extinction(const escg_params *p, uint8_t *d_lattice,
+                                      uint32_t mcs0, uint32_t max_mcs,
+                                      uint32_t mode, uint32_t *d_result,
+                                      void *stream)
+{
+    escg_status s = validate(p);
+    if (s != ESCG_OK)
+        return s;
+    if (!d_lattice || !d_result || !aligned4(d_lattice) ||
+        mode > ESCG_STOP_NONE)
+        return ESCG_EINVAL;
+    hipStream_t st = S_(stream);
+    const Derived d = derive(p);
+    const uint32_t L = p->L, S = p->S, N = L * L;
+    if (L <= lds_max_L()) {
+        JobDev J = make_job(p, d, 0, mcs0, max_mcs, mode, 0, nullptr,
+                            d_result, S + 3);
+        return launch_lds_single(J, d.small, d_lattice, st);
+    }
+    // Large lattice: tile MCS launches with a device stop flag, polled by
+    // the host every chunk.
+    uint8_t *scratch = nullptr;
+    const size_t flags_off = ((size_t)N + 255) & ~(size_t)255;
+    if (hipMallocAsync((void **)&scratch, flags_off + 512, st) != hipSuccess)
+        return ESCG_ENOMEM;
+    uint8_t *other = scratch;
+    uint32_t *stw = reinterpret_cast<uint32_t *>(scratch + flags_off);
+    uint32_t *cnt2 = stw + 4; // two rows of 32 counts
+    launch_fill(stw, 4 + 64, 0, st);
+    s = launch_densities(d_lattice, N, S, cnt2, st);
+    if (s != ESCG_OK)
+        return s;
+    hipLaunchKernelGGL(check_stop_kernel, dim3(1), dim3(64), 0, st, stw, cnt2,
+                       0u, S, mode, 0u, d_result);
+    TileArgs a = tile_args(p, d);
+    a.done = stw;
+    uint8_t *cur = d_lattice, *nxt = other;
+    uint32_t launched = 0;
+    const uint32_t chunk = 32;
+    while (launched < max_mcs) {
+        uint32_t done = 0;
+        if (hipMemcpyAsync(&done, stw, sizeof(done), hipMemcpyDeviceToHost,
+                           st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            (void)hipFreeAsync(scratch, st);
+            return ESCG_EDEVICE;
+        }
+        if (done)
+            break;
+        const uint32_t n = std::min(chunk, max_mcs - launched);
+        for (uint32_t k = 0; k < n; ++k) {
+            const uint32_t t = launched + k;
+            a.src = cur;
+            a.dst = nxt;
+            a.t = mcs0 + t;
+            a.counts = cnt2 + ((t + 1) & 1u) * 32;
+            launch_tile_mcs(a, d.small, st);
+            hipLaunchKernelGGL(check_stop_kernel, dim3(1), dim3(64), 0, st,
+                               stw, cnt2, (t + 1) & 1u, S, mode, t + 1,
+                               d_result);
+            std::swap(cur, nxt);
+        }
+        launched += n;
+    }
+    if (cur != d_lattice)
+        launch_copy(d_lattice, cur, N, st);
+    s = last_hip(hipGetLastError());
+    (void)hipFreeAsync(scratch, st);
+    return s;
+}
+
+uint32_t escg_batch_max_L(void) { return lds_max_L(); }
+
+escg_status escg_set_single_lds_max_L(uint32_t L)
+{
+    g_single_lds_max_L = L;
+    return ESCG_OK;
+}
+
+escg_status escg_batch_run(uint32_t n, const escg_params *h_params,
+                           const uint64_t *h_offsets, uint8_t *d_lattices,
+                           const uint32_t *h_mcs0, const uint32_t *h_max_mcs,
+                           uint32_t mode, uint32_t init, uint32_t *d_results,
+                           void *stream)
+{
+    if (n == 0)
+        return ESCG_OK;
+    if (!h_params || !h_offsets || !d_lattices || !h_max_mcs || !d_results ||
+        mode > ESCG_STOP_NONE || !aligned4(d_lattices))
+        return ESCG_EINVAL;
+    const uint32_t Lcap = lds_max_L();
+    std::vector<JobDev> jobs(n);
+    std::vector<uint32_t> order(n);
+    uint32_t Lmax = 0;
+    bool all_small = true;
+    std::vector<std::pair<uint64_t, uint64_t>> spans(n);
+    for (uint32_t j = 0; j < n; ++j) {
+        const escg_params *p = &h_params[j];
+        escg_status s = validate(p);
+        if (s != ESCG_OK)
+            return s;
+        if (p->L > Lcap)
+            return ESCG_EINVAL;
+        if (h_offsets[j] & 3u)
+            return ESCG_EINVAL;
+        const Derived d = derive(p);
+        all_small = all_small && d.small;
+        Lmax = std::max(Lmax, p->L);
+        jobs[j] = make_job(p, d, h_offsets[j], h_mcs0 ? h_mcs0[j] : 0,
+                           h_max_mcs[j], mode, init ? 1u : 0u, nullptr,
+                           d_results + (size_t)j * kResultWords, kResultWords);
+        spans[j] = {h_offsets[j], h_offsets[j] + (uint64_t)p->L * p->L};
+    }
+    {
+        std::vector<std::pair<uint64_t, uint64_t>> sp = spans;
+        std::sort(sp.begin(), sp.end());
+        for (uint32_t j = 1; j < n; ++j)
+            if (sp[j].first < sp[j - 1].second)
+                return ESCG_EINVAL;
+    }
+    // Longest jobs first (cost ~ L^2 * MCS budget).
+    for (uint32_t j = 0; j < n; ++j)
+        order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        const double ca = (double)jobs[a].L * jobs[a].L * jobs[a].max_mcs;
+        const double cb = (double)jobs[b].L * jobs[b].L * jobs[b].max_mcs;
+        return ca > cb;
+    });
+    hipStream_t st = S_(stream);
+    const size_t tbl = sizeof(JobDev) * n, ord = sizeof(uint32_t) * n;
+    uint8_t *dev = nullptr;
+    if (hipMallocAsync((void **)&dev, tbl + ord + 256, st) != hipSuccess)
+        return ESCG_ENOMEM;
+    JobDev *d_jobs = reinterpret_cast<JobDev *>(dev);
+    uint32_t *d_order = reinterpret_cast<uint32_t *>(dev + tbl);
+    uint32_t *d_queue = reinterpret_cast<uint32_t *>(dev + tbl + ord + 128);
+    escg_status s = ESCG_OK;
+    if (hipMemcpyAsync(d_jobs, jobs.data(), tbl, hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(d_order, order.data(), ord, hipMemcpyHostToDevice,
+                       st) != hipSuccess) {
+        (void)hipFreeAsync(dev, st);
+        return ESCG_EDEVICE;
+    }
+    launch_fill(d_queue, 1, 0, st);
+    const size_t lds = kLdsHeader + (size_t)Lmax * Lmax;
+    const uint32_t nt = lds_threads(Lmax);
+    const void *fn = all_small ? (const void *)lds_batch_kernel<true>
+                               : (const void *)lds_batch_kernel<false>;
+    allow_dynamic_lds(fn, lds);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nt, lds) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    const DeviceInfo di = device_info();
+    const uint32_t grid =
+        std::min<uint32_t>(n, (uint32_t)std::max(1, di.cus) * per_cu);
+    if (all_small)
+        hipLaunchKernelGGL(lds_batch_kernel<true>, dim3(grid), dim3(nt), lds,
+                           st, d_jobs, d_order, n, d_queue, d_lattices);
+    else
+        hipLaunchKernelGGL(lds_batch_kernel<false>, dim3(grid), dim3(nt), lds,
+                           st, d_jobs, d_order, n, d_queue, d_lattices);
+    s = last_hip(hipGetLastError());
+    (void)hipFreeAsync(dev, st);
+    return s;
+}
+
+} // extern "C"

@@ -1,0 +1,165 @@
+// escg_device.hpp -- device building blocks of the ESCG hot path on gfx950.
+//
+// Schedule and random-number contract (shared by every kernel here; the
+// result of a job is a pure function of it):
+//
+//   key      = (lo32(seed), hi32(seed)); every draw is one Philox4x32-10
+//              block (Salmon et al., SC'11) with counter (c0, c1, c2, c3)
+//   init     site n = row*L + col: word (n & 3) of counter
+//              (n >> 2, 0, kTagInit << 8, replica); value = (w * (S+1)) >> 32
+//   offsets  MCS t, pass p: word p of (0, t, kTagOffset << 8, replica);
+//              ox = bit 0, oy = bit 1
+//   blocks   pass p tiles the lattice into 2x2 blocks with top-left corner
+//              (2*by + oy, 2*bx + ox) mod L; block (by, bx) uses word
+//              (bx & 3) of counter (by*Q + (bx >> 2), t, (kTagPass << 8) | p,
+//              replica), Q = ceil((L/2) / 4) quads per block row
+//   word w   edge = w & 3: (A,B), (C,D), (A,C), (B,D) with A top-left,
+//              B top-right, C bottom-left, D bottom-right; bit 2 set: the
+//              second site of the edge is the selected cell; u = w >> 8 is
+//              the 24-bit action draw: exchange if u < T1, selection if
+//              u < T2, else reproduction
+//
+// The pair rule follows the paper's Algorithm "Elementary Step" (same
+// species: no change; migration swaps; interaction empties the dominated
+// site when both are occupied, the selected cell's win tested first;
+// reproduction fills an empty site with the other site's species), with the
+// Dominance Check algorithm as a bitmask test.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace escg {
+
+constexpr uint32_t kTagInit = 1u;
+constexpr uint32_t kTagOffset = 2u;
+constexpr uint32_t kTagPass = 3u;
+
+// Philox4x32 constants (Salmon et al., SC'11, Sec. 4): multipliers and the
+// Weyl key increments (golden ratio, sqrt(3) - 1).
+constexpr uint32_t kMulA = 0xD2511F53u;
+constexpr uint32_t kMulB = 0xCD9E8D57u;
+constexpr uint32_t kWeylA = 0x9E3779B9u;
+constexpr uint32_t kWeylB = 0xBB67AE85u;
+
+struct Words {
+    uint32_t w[4];
+};
+
+// Ten Philox rounds.  Counter words that are uniform across the wave (MCS
+// index, tag, replica) stay in scalar registers through the first rounds.
+__device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1,
+                                          uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t pa = (uint64_t)kMulA * c0;
+        const uint64_t pb = (uint64_t)kMulB * c2;
+        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)pb;
+        c3 = (uint32_t)pa;
+        c0 = n0;
+        c2 = n2;
+        k0 += kWeylA;
+        k1 += kWeylB;
+    }
+    Words o;
+    o.w[0] = c0; o.w[1] = c1; o.w[2] = c2; o.w[3] = c3;
+    return o;
+}
+
+__device__ __forceinline__ uint32_t pick(const Words &q, uint32_t i)
+{
+    // i in 0..3; selects without dynamic register indexing
+    const uint32_t lo = (i & 1u) ? q.w[1] : q.w[0];
+    const uint32_t hi = (i & 1u) ? q.w[3] : q.w[2];
+    return (i & 2u) ? hi : lo;
+}
+
+// Dominance for S <= 7: bit (a*8 + b) of a 64-bit word set iff a beats b.
+struct DomPacked {
+    uint64_t bits;
+    __device__ __forceinline__ bool beats(uint32_t a, uint32_t b) const
+    {
+        return (bits >> (((a << 3) | b) & 63u)) & 1u;
+    }
+};
+
+// Dominance for any S <= 31: per-species bitmasks staged in LDS.
+struct DomTable {
+    const uint32_t *dom; // 32 entries (LDS)
+    __device__ __forceinline__ bool beats(uint32_t a, uint32_t b) const
+    {
+        return (dom[a & 31u] >> (b & 31u)) & 1u;
+    }
+};
+
+// The pair rule on (x = selected cell, y = neighbour) for 24-bit draw u.
+template <class Dom>
+__device__ __forceinline__ void pair_rule(uint32_t u, uint32_t T1, uint32_t T2,
+                                          const Dom &d, uint32_t &x,
+                                          uint32_t &y)
+{
+    const uint32_t ox = x, oy = y;
+    uint32_t nx = ox, ny = oy;
+    if (u < T1) { // exchange
+        nx = oy;
+        ny = ox;
+    } else if (u < T2) { // selection
+        const bool diff = ox != oy;
+        if (diff && d.beats(ox, oy))
+            ny = 0;
+        else if (diff && d.beats(oy, ox))
+            nx = 0;
+    } else { // reproduction
+        if (oy == 0)
+            ny = ox;
+        else if (ox == 0)
+            nx = oy;
+    }
+    x = nx;
+    y = ny;
+}
+
+// Updates one 2x2 block in LDS.  pA..pD are the LDS byte offsets of the
+// block's top-left, top-right, bottom-left and bottom-right sites.
+template <class Dom>
+__device__ __forceinline__ void update_block(uint8_t *lat, uint32_t pA,
+                                             uint32_t pB, uint32_t pC,
+                                             uint32_t pD, uint32_t w,
+                                             uint32_t T1, uint32_t T2,
+                                             const Dom &d)
+{
+    const uint32_t e = w & 3u;
+    uint32_t f = (e & 2u) ? ((e & 1u) ? pB : pA) : ((e & 1u) ? pC : pA);
+    uint32_t s = (e & 2u) ? ((e & 1u) ? pD : pC) : ((e & 1u) ? pD : pB);
+    if (w & 4u) {
+        const uint32_t t = f;
+        f = s;
+        s = t;
+    }
+    uint32_t x = lat[f], y = lat[s];
+    pair_rule(w >> 8, T1, T2, d, x, y);
+    lat[f] = (uint8_t)x;
+    lat[s] = (uint8_t)y;
+}
+
+// Number of bytes of v that differ from s (valid for byte values < 0x80):
+// per byte, (b ^ s) + 0x7F sets bit 7 exactly when b != s, with no carry
+// into the next byte.
+__device__ __forceinline__ uint32_t bytes_ne(uint32_t v, uint32_t s)
+{
+    return __popc(((v ^ (s * 0x01010101u)) + 0x7F7F7F7Fu) & 0x80808080u);
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+} // namespace escg

@@ -1,0 +1,28 @@
+"""Helpers shared by the GPU tests: build matching (library, oracle) jobs from
+one description, and move arrays between numpy and the device."""
+import numpy as np
+
+import oracle as O
+from paper_2508_16639_amd import escg
+
+
+def pair(L, S, K, ex, sel=1.0, rep=1.0, seed=1, replica=0, D=None):
+    """The same job for the HIP library (escg.Params) and the oracle."""
+    if D is None:
+        D = O.circulant_matrix(S, K) if K else np.zeros((S, S), np.uint8)
+    p = escg.Params(L=L, S=S, dom=escg.dom_from_matrix(D), ex=ex, sel=sel,
+                    rep=rep, seed=seed, replica=replica)
+    j = O.Job(L, S, D, ex, sel, rep, seed=seed, replica=replica)
+    return p, j
+
+
+def dev(a, device="cuda:0"):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device)
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    a = t.cpu().numpy()
+    return a.view(np.uint32) if a.dtype == np.int32 else a

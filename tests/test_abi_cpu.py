@@ -1,0 +1,121 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/escg.h, and its host-side parameter preparation (dominance
+bitmasks, action thresholds, validation) agrees with the oracle."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2508_16639_amd import escg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "escg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(escg_\w+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("escg_init", "escg_step_mcs", "escg_densities",
+              "escg_run_until_extinction", "escg_batch_run"):
+        assert n in names
+    assert set(names) == set(escg.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = escg.lib()
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+
+
+def test_status_strings():
+    assert escg.status_str(0) == "ok"
+    assert escg.status_str(-1) == "invalid argument"
+
+
+@pytest.mark.parametrize("S,K", [(3, [1]), (5, [1, 3]), (5, [1, 2]),
+                                 (8, [1, 2, 5]), (31, [1, 7, 30]), (1, [])])
+def test_dominance_bitmasks_match_oracle_matrix(S, K):
+    D = O.circulant_matrix(S, K) if K else np.zeros((S, S), np.uint8)
+    dom = escg.circulant_dom(S, K)
+    assert dom == escg.dom_from_matrix(D)
+    for a in range(1, S + 1):
+        for b in range(1, S + 1):
+            assert ((dom[a] >> b) & 1) == D[a - 1, b - 1]
+    assert dom[0] == 0 and all((d & 1) == 0 for d in dom)
+
+
+@pytest.mark.parametrize("rates", [(0.5, 1, 1), (13.1072, 1, 1), (51.2, 1, 1),
+                                   (0, 1, 1), (1, 0, 1), (1, 1, 0), (3, 2, 5),
+                                   (1e-9, 1, 1), (1280.0, 1, 1)])
+def test_thresholds_match_oracle(rates):
+    p = escg.Params(L=8, S=3, dom=escg.circulant_dom(3, [1]), ex=rates[0],
+                    sel=rates[1], rep=rates[2])
+    assert escg.thresholds(p) == O.thresholds(*rates)
+
+
+def _bad_params():
+    good = dict(L=8, S=3, dom=escg.circulant_dom(3, [1]), ex=1.0)
+    yield dict(good, L=7)
+    yield dict(good, L=0)
+    yield dict(good, L=46342)
+    yield dict(good, S=0)
+    yield dict(good, S=32)
+    yield dict(good, ex=-1.0)
+    yield dict(good, ex=float("nan"))
+    yield dict(good, ex=float("inf"))
+    yield dict(good, ex=0.0, sel=0.0, rep=0.0)
+    yield dict(good, dom=[1] + [0] * 31)            # dom[0] set
+    yield dict(good, dom=[0, 1 << 5] + [0] * 30)    # bit above S
+    yield dict(good, dom=[0, 1] + [0] * 30)         # bit 0 set
+    yield dict(good, dom=[0, 2, 4, 8, 2] + [0] * 27)  # species 4 > S
+
+
+@pytest.mark.parametrize("kw", list(_bad_params()))
+def test_invalid_params_rejected_before_any_device_work(kw):
+    p = escg.Params(**kw).c()
+    lib = escg.lib()
+    dummy = C.c_void_p(4096)  # never dereferenced: validation fails first
+    res = C.c_void_p(8192)
+    assert lib.escg_init(C.byref(p), dummy, None) == escg.EINVAL
+    assert lib.escg_step_mcs(C.byref(p), dummy, 0, 1, None, None) == escg.EINVAL
+    assert lib.escg_densities(C.byref(p), dummy, res, None) == escg.EINVAL
+    assert lib.escg_run_until_extinction(C.byref(p), dummy, 0, 1, 0, res,
+                                         None) == escg.EINVAL
+
+
+def test_null_and_misaligned_pointers_rejected():
+    p = escg.Params(L=8, S=3, dom=escg.circulant_dom(3, [1]), ex=1.0).c()
+    lib = escg.lib()
+    assert lib.escg_init(C.byref(p), None, None) == escg.EINVAL
+    assert lib.escg_init(C.byref(p), C.c_void_p(4097), None) == escg.EINVAL
+    assert lib.escg_densities(C.byref(p), C.c_void_p(4096), None,
+                              None) == escg.EINVAL
+    assert lib.escg_run_until_extinction(C.byref(p), C.c_void_p(4096), 0, 1,
+                                         7, C.c_void_p(64), None) == escg.EINVAL
+    assert lib.escg_init(None, C.c_void_p(4096), None) == escg.EINVAL
+
+
+def test_batch_rejects_overlap_and_bad_jobs():
+    lib = escg.lib()
+    P = escg.CParams * 2
+    ps = P(escg.Params(L=8, S=3, dom=escg.circulant_dom(3, [1]), ex=1).c(),
+           escg.Params(L=8, S=3, dom=escg.circulant_dom(3, [1]), ex=1).c())
+    mx = (C.c_uint32 * 2)(5, 5)
+    overl = (C.c_uint64 * 2)(0, 32)   # second lattice starts inside the first
+    assert lib.escg_batch_run(2, ps, overl, C.c_void_p(4096), None, mx, 0, 1,
+                              C.c_void_p(8192), None) == escg.EINVAL
+    mis = (C.c_uint64 * 2)(0, 66)     # not 4-byte aligned
+    assert lib.escg_batch_run(2, ps, mis, C.c_void_p(4096), None, mx, 0, 1,
+                              C.c_void_p(8192), None) == escg.EINVAL
+    ok = (C.c_uint64 * 2)(0, 64)
+    assert lib.escg_batch_run(2, ps, ok, C.c_void_p(4096), None, mx, 9, 1,
+                              C.c_void_p(8192), None) == escg.EINVAL
+    assert lib.escg_batch_run(0, None, None, None, None, None, 0, 1, None,
+                              None) == escg.OK

@@ -1,0 +1,167 @@
+"""Parity of the HIP path with the oracle's parallel schedule (O2): lattices,
+per-MCS counts, stop flags and times must be identical, byte for byte.
+All calls go through the C ABI via the ctypes binding."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2508_16639_amd import escg
+from paper_2508_16639_amd.workloads import (RPS64, RPS512, RPSLS3200,
+                                            random_lattice)
+from tests.gpu_util import dev, host, pair
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(autouse=True)
+def _default_routing():
+    escg.set_single_lds_max_L(192)
+    yield
+    escg.set_single_lds_max_L(192)
+
+
+def gpu_step(p, g0, mcs0, n, want_counts=True):
+    lat = dev(g0)
+    cnt = (torch.full(((n + 1) * (p.S + 1),), -1, dtype=torch.int32,
+                      device="cuda:0") if want_counts else None)
+    escg.step_mcs(p, lat, mcs0, n, cnt)
+    out = host(lat)
+    c = host(cnt).reshape(n + 1, p.S + 1) if want_counts else None
+    return out, c
+
+
+@pytest.mark.parametrize("L", [2, 4, 6, 64, 100, 130, 512])
+@pytest.mark.parametrize("S", [1, 3, 5, 8])
+def test_init_bit_exact(L, S):
+    p, j = pair(L, S, [1] if S > 1 else [], 1.0, seed=0xDEADBEEF12345, replica=7)
+    lat = torch.empty(L * L, dtype=torch.uint8, device="cuda:0")
+    escg.init(p, lat)
+    assert np.array_equal(host(lat), j.init())
+
+
+@pytest.mark.parametrize("L,S", [(2, 3), (64, 3), (130, 5), (1000, 8),
+                                 (512, 31)])
+def test_densities_bit_exact(L, S):
+    p, j = pair(L, S, [1], 1.0)
+    g = random_lattice(L, S, seed=L + S)
+    cnt = torch.full((S + 1,), -1, dtype=torch.int32, device="cuda:0")
+    escg.densities(p, dev(g), cnt)
+    assert np.array_equal(host(cnt), O.counts(g, L, S))
+
+
+CASES = [
+    # L, S, K, (ex, sel, rep), n_mcs
+    (2, 3, [1], (1.0, 1.0, 1.0), 20),
+    (4, 3, [1], (0.5, 1.0, 1.0), 20),
+    (6, 5, [1, 3], (2.0, 1.0, 1.0), 15),
+    (8, 2, [1], (0.0, 1.0, 1.0), 15),
+    (10, 1, [], (1.0, 1.0, 1.0), 10),
+    (16, 8, [1, 2, 5], (1.0, 0.0, 1.0), 10),
+    (62, 5, [1, 2], (0.3, 1.0, 0.0), 8),
+    (64, 3, [1], (0.5, 1.0, 1.0), 12),
+    (100, 5, [1, 3], (13.0, 1.0, 1.0), 6),
+    (130, 3, [1], (1.0, 1.0, 1.0), 5),
+    (192, 31, [1, 4, 9, 16], (0.7, 1.0, 1.3), 3),
+    (200, 3, [1], (2.0, 1.0, 1.0), 3),
+    (256, 5, [1, 3], (51.2, 1.0, 1.0), 3),
+    (258, 3, [1], (1.0, 1.0, 1.0), 3),
+    (404, 5, [1, 3], (1.0, 1.0, 1.0), 2),
+    (520, 8, [1, 3], (5.0, 1.0, 1.0), 2),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"L{c[0]}_S{c[1]}")
+@pytest.mark.parametrize("route", ["auto", "tiled", "lds"])
+def test_step_mcs_bit_exact(case, route):
+    L, S, K, rates, n = case
+    if route == "tiled":
+        if L < 16:
+            pytest.skip("tiled path not used below L=16")
+        escg.set_single_lds_max_L(0)
+    elif route == "lds":
+        if L > escg.batch_max_L():
+            pytest.skip("lattice does not fit LDS")
+        escg.set_single_lds_max_L(100000)
+    p, j = pair(L, S, K, *rates, seed=L * 7 + S, replica=3)
+    g0 = random_lattice(L, S, seed=L, domain=3)
+    mcs0 = 41
+    out, c = gpu_step(p, g0, mcs0, n)
+    ref = g0.copy()
+    rc = O.o2_run(j, ref, mcs0, n)
+    assert np.array_equal(out, ref)
+    assert np.array_equal(c, rc)
+
+
+@pytest.mark.parametrize("route", ["lds", "tiled"])
+def test_zero_mcs_writes_only_row0(route):
+    escg.set_single_lds_max_L(100000 if route == "lds" else 0)
+    p, j = pair(64, 3, [1], 1.0)
+    g0 = random_lattice(64, 3, seed=1)
+    out, c = gpu_step(p, g0, 0, 0)
+    assert np.array_equal(out, g0)
+    assert np.array_equal(c[0], O.counts(g0, 64, 3))
+
+
+def test_workload_rps_L64_full():
+    w = RPS64
+    p, j = pair(w.L, w.S, list(w.K), w.ex, w.sel, w.rep, seed=w.seed)
+    lat = torch.empty(w.L * w.L, dtype=torch.uint8, device="cuda:0")
+    cnt = torch.empty((w.mcs + 1) * (w.S + 1), dtype=torch.int32,
+                      device="cuda:0")
+    escg.init(p, lat)
+    escg.step_mcs(p, lat, 0, w.mcs, cnt)
+    g = j.init()
+    rc = O.o2_run(j, g, 0, w.mcs)
+    assert np.array_equal(host(lat), g)
+    assert np.array_equal(host(cnt).reshape(rc.shape), rc)
+
+
+def test_workload_rps_L512_prefix():
+    w = RPS512
+    n = 120
+    p, j = pair(w.L, w.S, list(w.K), w.ex, w.sel, w.rep, seed=w.seed)
+    lat = torch.empty(w.L * w.L, dtype=torch.uint8, device="cuda:0")
+    escg.init(p, lat)
+    cnt = torch.empty((n + 1) * (w.S + 1), dtype=torch.int32, device="cuda:0")
+    escg.step_mcs(p, lat, 0, n, cnt)
+    g = j.init()
+    rc = O.o2_run(j, g, 0, n)
+    assert np.array_equal(host(lat), g)
+    assert np.array_equal(host(cnt).reshape(rc.shape), rc)
+
+
+def test_workload_rpsls_L3200_prefix():
+    w = RPSLS3200
+    n = 2
+    p, j = pair(w.L, w.S, list(w.K), w.ex, w.sel, w.rep, seed=w.seed)
+    lat = torch.empty(w.L * w.L, dtype=torch.uint8, device="cuda:0")
+    escg.init(p, lat)
+    cnt = torch.empty((n + 1) * (w.S + 1), dtype=torch.int32, device="cuda:0")
+    escg.step_mcs(p, lat, 0, n, cnt)
+    g = j.init()
+    rc = O.o2_run(j, g, 0, n)
+    assert np.array_equal(host(lat), g)
+    assert np.array_equal(host(cnt).reshape(rc.shape), rc)
+
+
+@pytest.mark.parametrize("route", ["lds", "tiled"])
+def test_resume_split_equals_straight(route):
+    escg.set_single_lds_max_L(100000 if route == "lds" else 0)
+    p, _ = pair(96, 5, [1, 3], 3.0, seed=5)
+    g0 = random_lattice(96, 5, seed=3)
+    a, ca = gpu_step(p, g0, 10, 9)
+    b, cb1 = gpu_step(p, g0, 10, 4)
+    b, cb2 = gpu_step(p, b, 14, 5)
+    assert np.array_equal(a, b)
+    assert np.array_equal(ca, np.vstack([cb1, cb2[1:]]))
+
+
+def test_exchange_only_is_a_permutation_large():
+    L, S = 1024, 5
+    p, _ = pair(L, S, [1, 3], 1.0, 0.0, 0.0)
+    g0 = random_lattice(L, S, seed=9)
+    out, c = gpu_step(p, g0, 0, 4)
+    assert (c == c[0]).all()
+    assert np.array_equal(np.sort(out), np.sort(g0))
