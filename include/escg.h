@@ -147,9 +147,9 @@ escg_status escg_run_until_extinction(const escg_params *p, uint8_t *d_lattice,
                                       uint32_t mode, uint32_t *d_result,
                                       void *stream);
 
-/* Largest L that escg_batch_run accepts (the whole lattice must fit one
- * workgroup's LDS). */
-uint32_t escg_batch_max_L(void);
+/* Largest L that escg_batch_run accepts for S species (the whole lattice and
+ * the S-dependent rule tables must fit one workgroup's LDS); 0 for invalid S. */
+uint32_t escg_batch_max_L(uint32_t S);
 
 /* Many independent jobs in one launch of a persistent kernel: each
  * workgroup takes jobs from a queue (longest first), keeps the job's
@@ -181,6 +181,19 @@ escg_status escg_batch_run(uint32_t n, const escg_params *h_params,
  * the same bytes; the knob only trades latency for occupancy.  Process-wide;
  * always ESCG_OK. */
 escg_status escg_set_single_lds_max_L(uint32_t L_max);
+
+/* Routing knob: escg_step_mcs runs lattices with L >= L_min (and L % 8 == 0)
+ * in one persistent cooperative launch that keeps every tile in LDS for all
+ * MCS (default 400); smaller or unsupported lattices use one launch per
+ * MCS.  Same bytes either way.  Process-wide; always ESCG_OK. */
+escg_status escg_set_persistent_min_L(uint32_t L_min);
+
+/* Synchronises the current device and reports errors that asynchronous
+ * kernels can only record on the device: ESCG_ETIMEOUT if a persistent
+ * kernel abandoned a bounded wait for a neighbouring workgroup since the
+ * last reset (its outputs are then invalid), else ESCG_OK (or ESCG_EDEVICE
+ * if the synchronisation fails).  reset != 0 clears the record. */
+escg_status escg_async_status(int reset);
 
 #ifdef __cplusplus
 }

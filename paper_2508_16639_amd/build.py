@@ -12,6 +12,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(PKG, "libescg.so")
 SOURCES = [os.path.join(CSRC, "escg.hip")]
 HEADERS = [os.path.join(CSRC, "escg_device.hpp"),
+           os.path.join(CSRC, "escg_quad.hpp"),
+           os.path.join(CSRC, "escg_lds.hpp"),
            os.path.join(INCLUDE, "escg.h")]
 ARCH = "gfx950"
 

@@ -18,6 +18,9 @@
 //
 // See escg_device.hpp for the schedule / random-number contract.
 #include "escg_device.hpp"
+#include "escg_quad.hpp"
+#include "escg_lds.hpp"
+#include "escg_tile.hpp"
 #include "escg.h"
 
 #include <algorithm>
@@ -26,14 +29,15 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 using namespace escg;
 
 namespace {
 
-constexpr uint32_t kLdsHeader = 512;    // dom table, counts, misc words
 constexpr uint32_t kResultWords = ESCG_BATCH_RESULT_WORDS;
 
 // ---------------------------------------------------------------------------
@@ -63,7 +67,8 @@ __device__ __forceinline__ bool stop_met(const uint32_t *c, uint32_t S,
 }
 
 // Counts sites of value 0..S among ndw dwords of LDS; adds into cnt[0..S]
-// (LDS, zeroed beforehand).
+// (LDS, zeroed beforehand).  Bytes that are not sites hold kPadByte, which
+// matches no species.
 template <int SM>
 __device__ __forceinline__ void count_dwords(const uint32_t *lat32,
                                              uint32_t ndw, uint32_t S,
@@ -92,84 +97,62 @@ __device__ __forceinline__ void count_dwords(const uint32_t *lat32,
     }
 }
 
-// One MCS (four passes) on an L x L lattice held whole in LDS.
-template <class Dom>
-__device__ __forceinline__ void lds_mcs(uint8_t *lat, const JobDev &J,
-                                        uint32_t t, uint32_t k0, uint32_t k1,
-                                        const Dom &dom, uint32_t by0,
-                                        uint32_t qx0, uint32_t dby,
-                                        uint32_t dqx)
-{
-    const uint32_t L = J.L, Lb = L >> 1, Q = (Lb + 3) >> 2, nq = Lb * Q;
-    const Words off = philox10(0u, t, kTagOffset << 8, J.replica, k0, k1);
-#pragma unroll
-    for (uint32_t p = 0; p < 4; ++p) {
-        const uint32_t ox = off.w[p] & 1u, oy = (off.w[p] >> 1) & 1u;
-        uint32_t by = by0, qx = qx0;
-        for (uint32_t qi = threadIdx.x; qi < nq; qi += blockDim.x) {
-            const Words r = philox10(qi, t, (kTagPass << 8) | p, J.replica,
-                                     k0, k1);
-            const uint32_t r0 = 2u * by + oy;
-            const uint32_t r1 = (r0 + 1u == L) ? 0u : r0 + 1u;
-            const uint32_t rowA = r0 * L, rowC = r1 * L;
-#pragma unroll
-            for (uint32_t j = 0; j < 4; ++j) {
-                const uint32_t bx = 4u * qx + j;
-                if (bx < Lb) {
-                    const uint32_t c0 = 2u * bx + ox;
-                    const uint32_t c1 = (c0 + 1u == L) ? 0u : c0 + 1u;
-                    update_block(lat, rowA + c0, rowA + c1, rowC + c0,
-                                 rowC + c1, r.w[j], J.T1, J.T2, dom);
-                }
-            }
-            qx += dqx;
-            by += dby;
-            if (qx >= Q) {
-                qx -= Q;
-                ++by;
-            }
-        }
-        __syncthreads();
-    }
-}
-
 template <bool kPacked>
 __device__ void run_job_lds(const JobDev &J, uint8_t *base, uint8_t *smem)
 {
-    uint32_t *s_dom = reinterpret_cast<uint32_t *>(smem);
-    uint32_t *s_cnt = s_dom + 32; // two rows of 32
-    uint8_t *lat = smem + kLdsHeader;
-    uint32_t *lat32 = reinterpret_cast<uint32_t *>(lat);
+    uint32_t *s_dom = reinterpret_cast<uint32_t *>(smem + kOffDom);
+    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(smem + kOffCnt);
     const uint32_t tid = threadIdx.x, nt = blockDim.x;
-    const uint32_t L = J.L, S = J.S, N = L * L, ndw = N >> 2;
+    const uint32_t L = J.L, S = J.S, LS = row_stride(L);
+    uint8_t *lat = smem + lattice_lds_offset(S);
+    uint32_t *lat32 = reinterpret_cast<uint32_t *>(lat);
     const uint32_t k0 = (uint32_t)J.seed, k1 = (uint32_t)(J.seed >> 32);
     uint8_t *g = base + J.lat_off;
-    uint32_t *g32 = reinterpret_cast<uint32_t *>(g);
 
     if (tid < 32)
         s_dom[tid] = J.dom[tid];
     if (tid < 64)
         s_cnt[tid] = 0;
+    // row padding bytes match no species
+    if (LS != L)
+        for (uint32_t r = tid; r < L; r += nt)
+            for (uint32_t c = L; c < LS; ++c)
+                lat[r * LS + c] = kPadByte;
     if (J.init) {
-        for (uint32_t i = tid; i < ndw; i += nt) {
+        const uint32_t nw = (L * L) >> 2;
+        for (uint32_t i = tid; i < nw; i += nt) {
             const Words w = philox10(i, 0u, kTagInit << 8, J.replica, k0, k1);
-            uint32_t v = 0;
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                v |= (uint32_t)(((uint64_t)w.w[j] * (S + 1u)) >> 32) << (8 * j);
-            lat32[i] = v;
+            for (uint32_t j = 0; j < 4; ++j) {
+                const uint32_t n = 4u * i + j, r = n / L, c = n - r * L;
+                lat[r * LS + c] =
+                    (uint8_t)(((uint64_t)pick(w, j) * (S + 1u)) >> 32);
+            }
+        }
+    } else if ((L & 3u) == 0) {
+        const uint32_t dwr = L >> 2, nw = L * dwr;
+        const uint32_t *g32 = reinterpret_cast<const uint32_t *>(g);
+        for (uint32_t i = tid; i < nw; i += nt) {
+            const uint32_t r = i / dwr, c = i - r * dwr;
+            lat32[(r * LS >> 2) + c] = g32[i];
         }
     } else {
-        for (uint32_t i = tid; i < ndw; i += nt)
-            lat32[i] = g32[i];
+        const uint32_t hr = L >> 1, nh = L * hr;
+        const uint16_t *g16 = reinterpret_cast<const uint16_t *>(g);
+        for (uint32_t i = tid; i < nh; i += nt) {
+            const uint32_t r = i / hr, c = i - r * hr;
+            reinterpret_cast<uint16_t *>(lat)[(r * LS >> 1) + c] = g16[i];
+        }
     }
     __syncthreads();
-
-    DomPacked dp{J.dom_packed};
-    DomTable dt{s_dom};
+    build_quad_luts(reinterpret_cast<uint2 *>(smem + kOffSel),
+                    reinterpret_cast<uint16_t *>(smem + kOffRule),
+                    species_pow2(S), s_dom);
+    const QuadCtx qc = make_quad_ctx(smem, S, J.T1, J.T2);
     const uint32_t Lb = L >> 1, Q = (Lb + 3) >> 2;
     const uint32_t by0 = tid / Q, qx0 = tid - by0 * Q;
     const uint32_t dby = nt / Q, dqx = nt - dby * Q;
+    const uint32_t ndw = (LS * L) >> 2;
 
     uint32_t cur = 0;
     if (kPacked)
@@ -185,10 +168,8 @@ __device__ void run_job_lds(const JobDev &J, uint8_t *base, uint8_t *smem)
         const uint32_t nxt = cur ^ 1u;
         if (tid < 32)
             s_cnt[nxt * 32 + tid] = 0;
-        if (kPacked)
-            lds_mcs(lat, J, J.mcs0 + t, k0, k1, dp, by0, qx0, dby, dqx);
-        else
-            lds_mcs(lat, J, J.mcs0 + t, k0, k1, dt, by0, qx0, dby, dqx);
+        lds_mcs(lat, L, LS, J.mcs0 + t, J.replica, k0, k1, qc, by0, qx0, dby,
+                dqx);
         if (kPacked)
             count_dwords<8>(lat32, ndw, S, s_cnt + nxt * 32);
         else
@@ -200,8 +181,21 @@ __device__ void run_job_lds(const JobDev &J, uint8_t *base, uint8_t *smem)
         if (J.counts && tid <= S)
             J.counts[(size_t)t * (S + 1) + tid] = s_cnt[cur * 32 + tid];
     }
-    for (uint32_t i = tid; i < ndw; i += nt)
-        g32[i] = lat32[i];
+    if ((L & 3u) == 0) {
+        const uint32_t dwr = L >> 2, nw = L * dwr;
+        uint32_t *g32 = reinterpret_cast<uint32_t *>(g);
+        for (uint32_t i = tid; i < nw; i += nt) {
+            const uint32_t r = i / dwr, c = i - r * dwr;
+            g32[i] = lat32[(r * LS >> 2) + c];
+        }
+    } else {
+        const uint32_t hr = L >> 1, nh = L * hr;
+        uint16_t *g16 = reinterpret_cast<uint16_t *>(g);
+        for (uint32_t i = tid; i < nh; i += nt) {
+            const uint32_t r = i / hr, c = i - r * hr;
+            g16[i] = reinterpret_cast<const uint16_t *>(lat)[(r * LS >> 1) + c];
+        }
+    }
     if (J.result) {
         for (uint32_t i = tid; i < J.result_words; i += nt) {
             uint32_t v = 0;
@@ -417,6 +411,117 @@ __global__ __launch_bounds__(kTileThreads) void tile_mcs_kernel(TileArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Large lattices: persistent tiled kernel (one launch for all MCS)
+// ---------------------------------------------------------------------------
+
+// Sticky per-device error word: set when a persistent kernel's bounded wait
+// for a neighbour gives up (only possible if its workgroups were not all
+// resident).  Read and cleared by escg_async_status().
+__device__ uint32_t g_async_error;
+
+struct TiledArgs {
+    uint8_t *lattice;   // in/out
+    uint32_t *exch;     // 2 * T * slot_dwords exchange area
+    uint32_t *flags;    // T words, zeroed: MCS completed per tile
+    uint32_t *abort;    // 1 word, zeroed
+    uint32_t *counts;   // rows (n+1)*(S+1) with rows 1..n zeroed, or null
+    uint64_t seed;
+    TileGeom G;
+    uint32_t S, T1, T2, replica, mcs0, n_mcs, spin_limit;
+    uint32_t dom[32];
+};
+
+template <bool kPacked>
+__global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint32_t *s_dom = reinterpret_cast<uint32_t *>(smem + kOffDom);
+    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(smem + kOffCnt);
+    uint32_t *s_misc = s_cnt + 64;
+    uint8_t *lat = smem + lattice_lds_offset(a.S);
+    const TileGeom G = a.G;
+    const uint32_t tid = threadIdx.x, S = a.S;
+    const uint32_t T = G.TY * G.TX;
+    // XCD-aware: workgroups are dealt round-robin to the 8 XCDs, so give
+    // each XCD a contiguous band of tiles (neighbours share an L2).
+    const uint32_t b = blockIdx.x;
+    const uint32_t tile = (T % 8u == 0) ? (b & 7u) * (T >> 3) + (b >> 3) : b;
+    const uint32_t ty = tile / G.TX, tx = tile - (tile / G.TX) * G.TX;
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    const uint32_t sd = G.slot_dwords();
+
+    if (tid < 32)
+        s_dom[tid] = a.dom[tid];
+    if (tid < 64)
+        s_cnt[tid] = 0;
+    tile_load(lat, a.lattice, G, ty, tx);
+    __syncthreads();
+    build_quad_luts(reinterpret_cast<uint2 *>(smem + kOffSel),
+                    reinterpret_cast<uint16_t *>(smem + kOffRule),
+                    species_pow2(S), s_dom);
+    __syncthreads();
+    const QuadCtx qc = make_quad_ctx(smem, S, a.T1, a.T2);
+
+    bool aborted = false;
+    for (uint32_t t = 0; t < a.n_mcs; ++t) {
+        tile_mcs(lat, G, ty, tx, a.mcs0 + t, a.replica, k0, k1, qc);
+        const uint32_t slot = (t + 1) & 1u;
+        tile_publish(lat, a.exch + (size_t)(2 * tile + slot) * sd, G);
+        // the strips must have reached L2 before the flag is released
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (tid == 0)
+            __hip_atomic_store(&a.flags[tile], t + 1, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        if (a.counts) {
+            if (kPacked)
+                tile_count<8>(lat, G, S, s_cnt);
+            else
+                tile_count<32>(lat, G, S, s_cnt);
+        }
+        // wait for the eight neighbours (bounded)
+        if (tid < 9 && tid != 4) {
+            const uint32_t dy = tid / 3, dx = tid - dy * 3;
+            const uint32_t ny = (ty + G.TY + dy - 1) % G.TY;
+            const uint32_t nx = (tx + G.TX + dx - 1) % G.TX;
+            const uint32_t *f = &a.flags[ny * G.TX + nx];
+            uint32_t spins = 0;
+            while (__hip_atomic_load(f, __ATOMIC_ACQUIRE,
+                                     __HIP_MEMORY_SCOPE_AGENT) < t + 1) {
+                if (__hip_atomic_load(a.abort, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT))
+                    break;
+                if (++spins > a.spin_limit) {
+                    __hip_atomic_store(a.abort, 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    atomicOr(&g_async_error, 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __syncthreads();
+        if (a.counts && tid <= S) {
+            atomicAdd(&a.counts[(size_t)(t + 1) * (S + 1) + tid], s_cnt[tid]);
+            s_cnt[tid] = 0;
+        }
+        if (tid == 0)
+            s_misc[0] = __hip_atomic_load(a.abort, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        if (s_misc[0]) {
+            aborted = true;
+            break;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        tile_gather(lat, a.exch, G, ty, tx, slot);
+        __syncthreads();
+    }
+    if (!aborted)
+        tile_store(lat, a.lattice, G, ty, tx);
+}
+
+// ---------------------------------------------------------------------------
 // Small kernels
 // ---------------------------------------------------------------------------
 __global__ void init_kernel(uint32_t *lat32, uint32_t ndw, uint32_t S,
@@ -587,18 +692,21 @@ DeviceInfo device_info()
     return cache[dev];
 }
 
-uint32_t lds_max_L()
+size_t lds_job_bytes(uint32_t L, uint32_t S)
+{
+    return (size_t)lattice_lds_offset(S) + (size_t)row_stride(L) * L;
+}
+
+// Largest even L whose whole lattice (plus tables) fits one workgroup's LDS.
+uint32_t lds_max_L(uint32_t S)
 {
     const DeviceInfo di = device_info();
-    size_t lds = di.lds_max ? di.lds_max : 65536;
-    const size_t reserve = kLdsHeader + 64; // + static LDS of the kernels
-    if (lds <= reserve)
-        return 0;
-    uint32_t L = (uint32_t)std::floor(std::sqrt((double)(lds - reserve)));
-    L &= ~1u;
-    while (L > 0 && (size_t)L * L + reserve > lds)
-        L -= 2;
-    return L;
+    const size_t lds = di.lds_max ? di.lds_max : 65536;
+    const size_t reserve = 64; // static LDS of the kernels
+    uint32_t L = 2;
+    while (lds_job_bytes(L + 2, S) + reserve <= lds)
+        L += 2;
+    return lds_job_bytes(L, S) + reserve <= lds ? L : 0;
 }
 
 // Single jobs run in the LDS-resident kernel up to this L (one workgroup, so
@@ -657,7 +765,7 @@ uint32_t lds_threads(uint32_t Lmax) { return Lmax <= 128 ? 256u : 512u; }
 escg_status launch_lds_single(const JobDev &J, bool small, uint8_t *base,
                               hipStream_t st)
 {
-    const size_t lds = kLdsHeader + (size_t)J.L * J.L;
+    const size_t lds = lds_job_bytes(J.L, J.S);
     const uint32_t nt = lds_threads(J.L);
     if (small) {
         allow_dynamic_lds((const void *)lds_single_kernel<true>, lds);
@@ -730,6 +838,144 @@ void launch_tile_mcs(const TileArgs &a, bool small, hipStream_t st)
     else
         hipLaunchKernelGGL(tile_mcs_kernel<false>, grid, dim3(kTileThreads), 0,
                            st, a);
+}
+
+// Tile geometry for the persistent kernel: equal tiles, TW % 8 == 0, TH
+// even and >= 4, all tiles co-resident.  Cost model: the busiest CU's region
+// area (halo included) plus a fixed per-MCS synchronisation charge.
+struct TiledPlan {
+    bool ok = false;
+    TileGeom G{};
+    uint32_t threads = 0;
+    size_t lds = 0;
+};
+
+uint32_t tiled_threads(const TileGeom &G)
+{
+    const uint32_t items = (G.RH() / 2) * ((G.TW + 16) / 8);
+    uint32_t nt = (items + 63) / 64 * 64;
+    return std::min(1024u, std::max(64u, nt));
+}
+
+std::atomic<uint32_t> g_tiled_min_L{400};
+
+TiledPlan plan_tiled_uncached(uint32_t L, uint32_t S)
+{
+    TiledPlan best;
+    if (L % 8 != 0 || L < 16)
+        return best;
+    const DeviceInfo di = device_info();
+    const int cus = std::max(1, di.cus);
+    const size_t lds_max = di.lds_max ? di.lds_max : 65536;
+    double best_cost = 1e300;
+    for (uint32_t TW = 8; TW <= L; TW += 8) {
+        if (L % TW)
+            continue;
+        for (uint32_t TH = 4; TH <= L; TH += 2) {
+            if (L % TH)
+                continue;
+            TileGeom G{L, TH, TW, L / TH, L / TW};
+            const uint32_t T = G.TY * G.TX;
+            const size_t lds = (size_t)lattice_lds_offset(S) +
+                               G.region_bytes() + 64;
+            if (lds > lds_max)
+                continue;
+            const uint32_t nt = tiled_threads(G);
+            const void *fn = S <= 7 ? (const void *)tiled_persistent_kernel<true>
+                                    : (const void *)tiled_persistent_kernel<false>;
+            allow_dynamic_lds(fn, lds);
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nt,
+                                                             lds) != hipSuccess)
+                (void)hipGetLastError();
+            if (per_cu < 1 || T > (uint32_t)cus * (uint32_t)per_cu)
+                continue;
+            const double waves = std::ceil((double)T / cus);
+            const double cost = waves * (double)(TH + 8) * (TW + 16) + 8000.0;
+            if (cost < best_cost) {
+                best_cost = cost;
+                best.ok = true;
+                best.G = G;
+                best.threads = nt;
+                best.lds = lds;
+            }
+        }
+    }
+    return best;
+}
+
+TiledPlan plan_tiled(uint32_t L, uint32_t S)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, uint32_t, bool>, TiledPlan> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const auto key = std::make_tuple(dev, L, S <= 7);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end())
+            return it->second;
+    }
+    const TiledPlan plan = plan_tiled_uncached(L, S <= 7 ? 7u : 31u);
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = plan;
+    return plan;
+}
+
+// Runs n_mcs MCS of a large lattice with the persistent kernel.  Returns
+// ESCG_EUNSUPPORTED (nothing enqueued) if no plan fits or the cooperative
+// launch is refused; the caller then uses the per-MCS tiled kernel.
+escg_status run_tiled_persistent(const escg_params *p, const Derived &d,
+                                 uint8_t *lattice, uint32_t mcs0,
+                                 uint32_t n_mcs, uint32_t *counts,
+                                 hipStream_t st)
+{
+    const TiledPlan plan = plan_tiled(p->L, p->S);
+    if (!plan.ok)
+        return ESCG_EUNSUPPORTED;
+    const TileGeom G = plan.G;
+    const uint32_t T = G.TY * G.TX;
+    const size_t exch_bytes = (size_t)2 * T * G.slot_dwords() * 4;
+    const size_t flags_off = (exch_bytes + 255) & ~(size_t)255;
+    const size_t total = flags_off + (size_t)(T + 64) * 4;
+    uint8_t *scr = nullptr;
+    if (hipMallocAsync((void **)&scr, total, st) != hipSuccess)
+        return ESCG_ENOMEM;
+    TiledArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.lattice = lattice;
+    a.exch = reinterpret_cast<uint32_t *>(scr);
+    a.flags = reinterpret_cast<uint32_t *>(scr + flags_off);
+    a.abort = a.flags + T;
+    a.counts = counts;
+    a.seed = p->seed;
+    a.G = G;
+    a.S = p->S;
+    a.T1 = d.T1;
+    a.T2 = d.T2;
+    a.replica = p->replica;
+    a.mcs0 = mcs0;
+    a.n_mcs = n_mcs;
+    a.spin_limit = 4000000u;
+    for (int i = 0; i < 32; ++i)
+        a.dom[i] = p->dom[i];
+    launch_fill(a.flags, T + 64, 0, st);
+    if (counts)
+        launch_fill(counts + (p->S + 1), (size_t)n_mcs * (p->S + 1), 0, st);
+    void *args[] = {&a};
+    const void *fn = d.small ? (const void *)tiled_persistent_kernel<true>
+                             : (const void *)tiled_persistent_kernel<false>;
+    allow_dynamic_lds(fn, plan.lds);
+    hipError_t e = hipLaunchCooperativeKernel(fn, dim3(T), dim3(plan.threads),
+                                              args, (unsigned)plan.lds, st);
+    escg_status s = ESCG_OK;
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        s = ESCG_EUNSUPPORTED;
+    }
+    (void)hipFreeAsync(scr, st);
+    return s;
 }
 
 bool aligned4(const void *p) { return ((uintptr_t)p & 3u) == 0; }
@@ -841,7 +1087,7 @@ escg_status escg_step_mcs(const escg_params *p, uint8_t *d_lattice,
     hipStream_t st = S_(stream);
     const Derived d = derive(p);
     const uint32_t L = p->L, S = p->S, N = L * L;
-    if (L <= std::min(g_single_lds_max_L.load(), lds_max_L())) {
+    if (L <= std::min(g_single_lds_max_L.load(), lds_max_L(S))) {
         JobDev J = make_job(p, d, 0, mcs0, n_mcs, ESCG_STOP_NONE, 0, d_counts,
                             nullptr, 0);
         return launch_lds_single(J, d.small, d_lattice, st);
@@ -854,6 +1100,12 @@ escg_status escg_step_mcs(const escg_params *p, uint8_t *d_lattice,
     }
     if (n_mcs == 0)
         return ESCG_OK;
+    if (L >= g_tiled_min_L.load()) {
+        s = run_tiled_persistent(p, d, d_lattice, mcs0, n_mcs, d_counts, st);
+        if (s != ESCG_EUNSUPPORTED)
+            return s;
+        s = ESCG_OK;
+    }
     uint8_t *other = nullptr;
     if (hipMallocAsync((void **)&other, N, st) != hipSuccess)
         return ESCG_ENOMEM;
@@ -888,7 +1140,7 @@ escg_status escg_run_until_extinction(const escg_params *p, uint8_t *d_lattice,
     hipStream_t st = S_(stream);
     const Derived d = derive(p);
     const uint32_t L = p->L, S = p->S, N = L * L;
-    if (L <= lds_max_L()) {
+    if (L <= lds_max_L(S)) {
         JobDev J = make_job(p, d, 0, mcs0, max_mcs, mode, 0, nullptr,
                             d_result, S + 3);
         return launch_lds_single(J, d.small, d_lattice, st);
@@ -945,12 +1197,38 @@ escg_status escg_run_until_extinction(const escg_params *p, uint8_t *d_lattice,
     return s;
 }
 
-uint32_t escg_batch_max_L(void) { return lds_max_L(); }
+uint32_t escg_batch_max_L(uint32_t S)
+{
+    return (S < 1 || S > ESCG_MAX_SPECIES) ? 0u : lds_max_L(S);
+}
 
 escg_status escg_set_single_lds_max_L(uint32_t L)
 {
     g_single_lds_max_L = L;
     return ESCG_OK;
+}
+
+escg_status escg_set_persistent_min_L(uint32_t L)
+{
+    g_tiled_min_L = L;
+    return ESCG_OK;
+}
+
+escg_status escg_async_status(int reset)
+{
+    if (hipDeviceSynchronize() != hipSuccess)
+        return last_hip(hipGetLastError());
+    uint32_t v = 0;
+    if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_async_error), sizeof(v), 0,
+                            hipMemcpyDeviceToHost) != hipSuccess)
+        return last_hip(hipGetLastError());
+    if (reset && v) {
+        const uint32_t z = 0;
+        if (hipMemcpyToSymbol(HIP_SYMBOL(g_async_error), &z, sizeof(z), 0,
+                              hipMemcpyHostToDevice) != hipSuccess)
+            return last_hip(hipGetLastError());
+    }
+    return v ? ESCG_ETIMEOUT : ESCG_OK;
 }
 
 escg_status escg_batch_run(uint32_t n, const escg_params *h_params,
@@ -964,10 +1242,10 @@ escg_status escg_batch_run(uint32_t n, const escg_params *h_params,
     if (!h_params || !h_offsets || !d_lattices || !h_max_mcs || !d_results ||
         mode > ESCG_STOP_NONE || !aligned4(d_lattices))
         return ESCG_EINVAL;
-    const uint32_t Lcap = lds_max_L();
     std::vector<JobDev> jobs(n);
     std::vector<uint32_t> order(n);
     uint32_t Lmax = 0;
+    size_t lds_need = 0;
     bool all_small = true;
     std::vector<std::pair<uint64_t, uint64_t>> spans(n);
     for (uint32_t j = 0; j < n; ++j) {
@@ -975,13 +1253,14 @@ escg_status escg_batch_run(uint32_t n, const escg_params *h_params,
         escg_status s = validate(p);
         if (s != ESCG_OK)
             return s;
-        if (p->L > Lcap)
+        if (p->L > lds_max_L(p->S))
             return ESCG_EINVAL;
         if (h_offsets[j] & 3u)
             return ESCG_EINVAL;
         const Derived d = derive(p);
         all_small = all_small && d.small;
         Lmax = std::max(Lmax, p->L);
+        lds_need = std::max(lds_need, lds_job_bytes(p->L, p->S));
         jobs[j] = make_job(p, d, h_offsets[j], h_mcs0 ? h_mcs0[j] : 0,
                            h_max_mcs[j], mode, init ? 1u : 0u, nullptr,
                            d_results + (size_t)j * kResultWords, kResultWords);
@@ -1019,7 +1298,7 @@ escg_status escg_batch_run(uint32_t n, const escg_params *h_params,
         return ESCG_EDEVICE;
     }
     launch_fill(d_queue, 1, 0, st);
-    const size_t lds = kLdsHeader + (size_t)Lmax * Lmax;
+    const size_t lds = lds_need;
     const uint32_t nt = lds_threads(Lmax);
     const void *fn = all_small ? (const void *)lds_batch_kernel<true>
                                : (const void *)lds_batch_kernel<false>;

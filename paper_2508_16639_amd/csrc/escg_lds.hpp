@@ -1,0 +1,106 @@
+// escg_lds.hpp -- one Monte Carlo step on a lattice held whole in LDS.
+//
+// Layout (byte offsets from the kernel's dynamic LDS base): dominance masks,
+// two count rows, the quad selector table, the rule tables, then the lattice
+// with row stride LS = L rounded up to 8 (padding bytes hold kPadByte).
+#pragma once
+
+#include "escg_quad.hpp"
+
+namespace escg {
+
+// LDS layout of the whole-lattice kernels (byte offsets).
+constexpr uint32_t kOffDom = 0;      // 32 u32 dominance masks
+constexpr uint32_t kOffCnt = 128;    // 2 x 32 u32 count rows
+constexpr uint32_t kOffSel = 512;    // 256 uint2 selectors
+constexpr uint32_t kOffRule = 2560;  // 3 * Sp * Sp u16 rule tables
+constexpr uint8_t kPadByte = 0x40;   // row padding: matches no species
+
+__host__ __device__ inline uint32_t species_pow2(uint32_t S)
+{
+    uint32_t sp = 8;
+    while (sp < S + 1)
+        sp <<= 1;
+    return sp;
+}
+__host__ __device__ inline uint32_t lattice_lds_offset(uint32_t S)
+{
+    const uint32_t sp = species_pow2(S);
+    return (kOffRule + 6 * sp * sp + 15) & ~15u;
+}
+__host__ __device__ inline uint32_t row_stride(uint32_t L)
+{
+    return (L + 7) & ~7u;
+}
+
+// One MCS (four passes) on an L x L lattice held whole in LDS with row
+// stride LS.  Work item = one quad (by, qx); the quad's Philox counter is
+// by*Q + qx, the index of the work item.
+__device__ __forceinline__ void lds_mcs(uint8_t *lat, uint32_t L, uint32_t LS,
+                                        uint32_t t, uint32_t replica,
+                                        uint32_t k0, uint32_t k1,
+                                        const QuadCtx &qc, uint32_t by0,
+                                        uint32_t qx0, uint32_t dby,
+                                        uint32_t dqx)
+{
+    const uint32_t Lb = L >> 1, Q = (Lb + 3) >> 2, nq = Lb * Q;
+    const Words off = philox10(0u, t, kTagOffset << 8, replica, k0, k1);
+#pragma unroll
+    for (uint32_t p = 0; p < 4; ++p) {
+        const uint32_t ox = off.w[p] & 1u, oy = (off.w[p] >> 1) & 1u;
+        const uint32_t ctr2 = (kTagPass << 8) | p;
+        uint32_t by = by0, qx = qx0;
+        for (uint32_t qi = threadIdx.x; qi < nq; qi += blockDim.x) {
+            const Words r = philox10(qi, t, ctr2, replica, k0, k1);
+            const uint32_t r0 = 2u * by + oy;
+            const uint32_t r1 = (r0 + 1u == L) ? 0u : r0 + 1u;
+            const uint32_t rowA = r0 * LS, rowC = r1 * LS;
+            const uint32_t col = 8u * qx;
+            if (4u * qx + 4u <= Lb) {
+                if (ox == 0) {
+                    quad_even(lat, rowA + col, rowC + col, r, qc);
+                } else {
+                    const uint32_t e = (col + 8u == L) ? 0u : col + 8u;
+                    quad_odd(lat, rowA + col, rowC + col, rowA + e, rowC + e,
+                             r, qc);
+                }
+            } else {
+                // last quad of a row with fewer than four blocks
+                for (uint32_t j = 0; j < 4; ++j) {
+                    if (4u * qx + j < Lb) {
+                        const uint32_t c0 = col + 2u * j + ox;
+                        const uint32_t c1 = (c0 + 1u == L) ? 0u : c0 + 1u;
+                        block_bytes(lat, rowA + c0, rowA + c1, rowC + c0,
+                                    rowC + c1, pick(r, j), qc);
+                    }
+                }
+            }
+            qx += dqx;
+            by += dby;
+            if (qx >= Q) {
+                qx -= Q;
+                ++by;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__device__ inline QuadCtx make_quad_ctx(uint8_t *smem, uint32_t S,
+                                        uint32_t T1, uint32_t T2)
+{
+    QuadCtx qc;
+    qc.sel = reinterpret_cast<const uint2 *>(smem + kOffSel);
+    qc.rule = smem + kOffRule;
+    const uint32_t sp = species_pow2(S);
+    const ActionSplit a = split_actions(T1, T2);
+    qc.W1 = a.W1;
+    qc.W2 = a.W2;
+    qc.B1 = a.a1 * sp * sp * 2u;
+    qc.B2 = a.a2 * sp * sp * 2u;
+    qc.B3 = a.a3 * sp * sp * 2u;
+    qc.dotw = (2u * sp) | (2u << 8);
+    return qc;
+}
+
+} // namespace escg

@@ -1,0 +1,193 @@
+// escg_quad.hpp -- branch-free update of four horizontally adjacent 2x2 blocks
+// ("a quad": one Philox call) held in LDS.
+//
+// A quad covers two lattice rows (a = top, c = bottom) and eight columns.
+// The two 8-byte row segments are transposed with v_perm into one dword per
+// block, B = [A, B, C, D] (top-left, top-right, bottom-left, bottom-right).
+// For block word w:
+//   * the low byte of w indexes an LDS table of two v_perm selectors: the
+//     gather selector moves (selected cell, neighbour) = (x, y) into bytes
+//     0 and 1; the scatter selector writes (x', y') back into their places
+//     and keeps the other two sites.  Bits 0-1 (edge) and 2 (orientation)
+//     decide them; bits 3-7 are unused, so the table repeats every 8 entries.
+//   * the action is picked by comparing w with thresholds pre-shifted into
+//     word space (u = w >> 8 < T  <=>  w <= (T << 8) - 1), which selects
+//     one of three rule tables;
+//   * the pair rule is one LDS lookup: rule[action][x][y] = x' | y' << 8,
+//     addressed by v_dot4_u32_u8(xy, {2*Sp, 2, 0, 0}, base).
+// Same species, exchange, selection and reproduction are all table entries,
+// so there are no branches and no equality test.
+#pragma once
+
+#include "escg_device.hpp"
+
+namespace escg {
+
+// Per-job constants of the quad update (all uniform).
+struct QuadCtx {
+    const uint2 *sel;     // LDS: 256 {gather, scatter} selectors
+    const uint8_t *rule;  // LDS: rule tables, byte addressed
+    uint32_t W1, W2;      // word-space thresholds (w <= W1: first table ...)
+    uint32_t B1, B2, B3;  // byte offsets of the three rule tables to use
+    uint32_t dotw;        // {2*Sp, 2, 0, 0}
+};
+
+// Host-computed word-space thresholds and table choice for (T1, T2) in
+// [0, 2^24]: first = w <= W1 ? B1 : (w <= W2 ? B2 : B3), equivalent to
+// exchange if u < T1, selection if u < T2, else reproduction, u = w >> 8.
+struct ActionSplit {
+    uint32_t W1, W2, a1, a2, a3; // a* = action index 0 ex, 1 sel, 2 rep
+};
+
+__host__ __device__ inline ActionSplit split_actions(uint32_t T1, uint32_t T2)
+{
+    ActionSplit s;
+    // w <= (T << 8) - 1 is u < T for T >= 1; T = 0 never holds, so the
+    // first comparison then maps to whatever the second one would give.
+    if (T1 >= 1) {
+        s.W1 = (uint32_t)(((uint64_t)T1 << 8) - 1);
+        s.a1 = 0;
+    } else {
+        s.W1 = 0;
+        s.a1 = T2 >= 1 ? 1u : 2u; // w == 0 -> u == 0: selection iff T2 >= 1
+    }
+    if (T2 >= 1) {
+        s.W2 = (uint32_t)(((uint64_t)T2 << 8) - 1);
+        s.a2 = 1;
+    } else {
+        s.W2 = 0;
+        s.a2 = 2;
+    }
+    s.a3 = 2;
+    return s;
+}
+
+// Builds the selector table (2 KB) and the rule tables (3*Sp*Sp u16) in LDS
+// with the workgroup's threads.  dom: 32 dominance masks (LDS or global).
+__device__ inline void build_quad_luts(uint2 *sel, uint16_t *rule, uint32_t Sp,
+                                       const uint32_t *dom)
+{
+    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) {
+        const uint32_t e = i & 3u, o = (i >> 2) & 1u;
+        // edge sites as byte positions of B = [A, B, C, D]
+        const uint32_t f = (e == 0) ? 0u : (e == 1) ? 2u : (e == 2) ? 0u : 1u;
+        const uint32_t s = (e == 0) ? 1u : (e == 1) ? 3u : (e == 2) ? 2u : 3u;
+        const uint32_t cell = o ? s : f, nbr = o ? f : s;
+        const uint32_t gather = cell | (nbr << 8) | 0x0C0C0000u;
+        uint32_t scatter = 0;
+        for (uint32_t b = 0; b < 4; ++b) {
+            const uint32_t src = (b == cell) ? 4u : (b == nbr) ? 5u : b;
+            scatter |= src << (8 * b);
+        }
+        sel[i] = make_uint2(gather, scatter);
+    }
+    const uint32_t n = 3 * Sp * Sp;
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const uint32_t a = i / (Sp * Sp), xy = i - a * Sp * Sp;
+        uint32_t x = xy / Sp, y = xy - (xy / Sp) * Sp;
+        const uint32_t u = a == 0 ? 0u : (a == 1 ? 1u : 2u);
+        // evaluate the pair rule with thresholds that force action a
+        DomTable dt{dom};
+        pair_rule(u, 1u, 2u, dt, x, y);
+        rule[i] = (uint16_t)(x | (y << 8));
+    }
+}
+
+__device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo,
+                                         uint32_t sel)
+{
+    return __builtin_amdgcn_perm(hi, lo, sel);
+}
+
+// One block: B = [A, B, C, D] -> updated dword.
+__device__ __forceinline__ uint32_t block_update(uint32_t B, uint32_t w,
+                                                 const QuadCtx &c)
+{
+    const uint2 s = c.sel[w & 0xFFu];
+    const uint32_t xy = perm(B, B, s.x);
+    const uint32_t base = (w <= c.W1) ? c.B1 : ((w <= c.W2) ? c.B2 : c.B3);
+    const uint32_t off = __builtin_amdgcn_udot4(xy, c.dotw, base, false);
+    const uint32_t out = *reinterpret_cast<const uint16_t *>(c.rule + off);
+    return perm(out, B, s.y);
+}
+
+// Row segments (8 bytes each, little-endian: byte k = column k of the
+// segment) -> four updated segments in place.
+__device__ __forceinline__ void quad_update(uint32_t &a0, uint32_t &a1,
+                                            uint32_t &c0, uint32_t &c1,
+                                            const Words &w, const QuadCtx &c)
+{
+    // transpose: block j = [a(2j), a(2j+1), c(2j), c(2j+1)]
+    uint32_t b0 = perm(a0, c0, 0x01000504u);
+    uint32_t b1 = perm(a0, c0, 0x03020706u);
+    uint32_t b2 = perm(a1, c1, 0x01000504u);
+    uint32_t b3 = perm(a1, c1, 0x03020706u);
+    b0 = block_update(b0, w.w[0], c);
+    b1 = block_update(b1, w.w[1], c);
+    b2 = block_update(b2, w.w[2], c);
+    b3 = block_update(b3, w.w[3], c);
+    // back to rows
+    a0 = perm(b1, b0, 0x05040100u);
+    c0 = perm(b1, b0, 0x07060302u);
+    a1 = perm(b3, b2, 0x05040100u);
+    c1 = perm(b3, b2, 0x07060302u);
+}
+
+// Quad whose columns start 8-byte aligned in LDS (offset ox = 0).
+__device__ __forceinline__ void quad_even(uint8_t *lat, uint32_t pa,
+                                          uint32_t pc, const Words &w,
+                                          const QuadCtx &c)
+{
+    uint2 ra = *reinterpret_cast<const uint2 *>(lat + pa);
+    uint2 rc = *reinterpret_cast<const uint2 *>(lat + pc);
+    quad_update(ra.x, ra.y, rc.x, rc.y, w, c);
+    *reinterpret_cast<uint2 *>(lat + pa) = ra;
+    *reinterpret_cast<uint2 *>(lat + pc) = rc;
+}
+
+// Quad whose columns start one byte after an 8-byte boundary (ox = 1):
+// pa / pc are the aligned addresses, ea / ec the addresses of the ninth byte
+// (the column after the 8-byte boundary, possibly wrapped by the caller).
+__device__ __forceinline__ void quad_odd(uint8_t *lat, uint32_t pa,
+                                         uint32_t pc, uint32_t ea,
+                                         uint32_t ec, const Words &w,
+                                         const QuadCtx &c)
+{
+    const uint2 ra = *reinterpret_cast<const uint2 *>(lat + pa);
+    const uint2 rc = *reinterpret_cast<const uint2 *>(lat + pc);
+    const uint32_t xa = lat[ea], xc = lat[ec];
+    uint32_t a0 = __builtin_amdgcn_alignbyte(ra.y, ra.x, 1);
+    uint32_t a1 = __builtin_amdgcn_alignbyte(xa, ra.y, 1);
+    uint32_t c0 = __builtin_amdgcn_alignbyte(rc.y, rc.x, 1);
+    uint32_t c1 = __builtin_amdgcn_alignbyte(xc, rc.y, 1);
+    quad_update(a0, a1, c0, c1, w, c);
+    // bytes 1..8 of the window: b8 at +1, b16 at +2, b32 at +4, b8 at +8
+    lat[pa + 1] = (uint8_t)a0;
+    *reinterpret_cast<uint16_t *>(lat + pa + 2) = (uint16_t)(a0 >> 8);
+    *reinterpret_cast<uint32_t *>(lat + pa + 4) =
+        __builtin_amdgcn_alignbyte(a1, a0, 3);
+    lat[ea] = (uint8_t)(a1 >> 24);
+    lat[pc + 1] = (uint8_t)c0;
+    *reinterpret_cast<uint16_t *>(lat + pc + 2) = (uint16_t)(c0 >> 8);
+    *reinterpret_cast<uint32_t *>(lat + pc + 4) =
+        __builtin_amdgcn_alignbyte(c1, c0, 3);
+    lat[ec] = (uint8_t)(c1 >> 24);
+}
+
+// One block addressed site by site (irregular quads: lattice edges with
+// wrap inside the quad, or blocks past the row end).
+__device__ __forceinline__ void block_bytes(uint8_t *lat, uint32_t pA,
+                                            uint32_t pB, uint32_t pC,
+                                            uint32_t pD, uint32_t w,
+                                            const QuadCtx &c)
+{
+    uint32_t B = (uint32_t)lat[pA] | ((uint32_t)lat[pB] << 8) |
+                 ((uint32_t)lat[pC] << 16) | ((uint32_t)lat[pD] << 24);
+    B = block_update(B, w, c);
+    lat[pA] = (uint8_t)B;
+    lat[pB] = (uint8_t)(B >> 8);
+    lat[pC] = (uint8_t)(B >> 16);
+    lat[pD] = (uint8_t)(B >> 24);
+}
+
+} // namespace escg

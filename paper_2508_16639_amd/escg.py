@@ -44,7 +44,8 @@ class CParams(C.Structure):
 EXPORTS = ("escg_status_str", "escg_last_error", "escg_circulant_dom", "escg_dom_from_matrix",
            "escg_thresholds", "escg_init", "escg_densities", "escg_step_mcs",
            "escg_run_until_extinction", "escg_batch_max_L", "escg_batch_run",
-           "escg_set_single_lds_max_L")
+           "escg_set_single_lds_max_L", "escg_set_persistent_min_L",
+           "escg_async_status")
 
 _lib = None
 
@@ -78,11 +79,13 @@ def lib():
     L.escg_densities.argtypes = [P, vp, vp, vp]
     L.escg_step_mcs.argtypes = [P, vp, u32, u32, vp, vp]
     L.escg_run_until_extinction.argtypes = [P, vp, u32, u32, u32, vp, vp]
-    L.escg_batch_max_L.argtypes = []
+    L.escg_batch_max_L.argtypes = [u32]
     L.escg_batch_max_L.restype = u32
     L.escg_batch_run.argtypes = [u32, P, C.POINTER(C.c_uint64), vp,
                                  u32p, u32p, u32, u32, vp, vp]
     L.escg_set_single_lds_max_L.argtypes = [u32]
+    L.escg_set_persistent_min_L.argtypes = [u32]
+    L.escg_async_status.argtypes = [C.c_int]
     for name in EXPORTS:
         if name not in ("escg_status_str", "escg_batch_max_L",
                         "escg_last_error"):
@@ -157,8 +160,18 @@ def thresholds(p: Params):
     return t1.value, t2.value
 
 
-def batch_max_L() -> int:
-    return int(lib().escg_batch_max_L())
+def batch_max_L(S: int = 3) -> int:
+    return int(lib().escg_batch_max_L(int(S)))
+
+
+def set_persistent_min_L(L: int) -> None:
+    _check(lib().escg_set_persistent_min_L(int(L)),
+           "escg_set_persistent_min_L")
+
+
+def async_status(reset: bool = True) -> None:
+    """Raises EscgError if an asynchronous kernel recorded a device error."""
+    _check(lib().escg_async_status(1 if reset else 0), "escg_async_status")
 
 
 def set_single_lds_max_L(L: int) -> None:

@@ -119,3 +119,10 @@ def test_batch_rejects_overlap_and_bad_jobs():
                               C.c_void_p(8192), None) == escg.EINVAL
     assert lib.escg_batch_run(0, None, None, None, None, None, 0, 1, None,
                               None) == escg.OK
+
+
+def test_routing_knobs_and_limits_callable_without_gpu():
+    escg.set_single_lds_max_L(192)
+    escg.set_persistent_min_L(400)
+    assert escg.batch_max_L(0) == 0 and escg.batch_max_L(32) == 0
+    assert escg.batch_max_L(3) >= escg.batch_max_L(31) > 0

@@ -15,11 +15,28 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
+def route_to(route):
+    """Force one of the three MCS paths (all must give the same bytes)."""
+    if route == "lds":
+        escg.set_single_lds_max_L(100000)
+        escg.set_persistent_min_L(100000)
+    elif route == "tiled":
+        escg.set_single_lds_max_L(0)
+        escg.set_persistent_min_L(100000)
+    elif route == "persistent":
+        escg.set_single_lds_max_L(0)
+        escg.set_persistent_min_L(0)
+    else:
+        escg.set_single_lds_max_L(192)
+        escg.set_persistent_min_L(400)
+
+
 @pytest.fixture(autouse=True)
 def _default_routing():
-    escg.set_single_lds_max_L(192)
+    route_to("auto")
     yield
-    escg.set_single_lds_max_L(192)
+    route_to("auto")
+    escg.async_status()
 
 
 def gpu_step(p, g0, mcs0, n, want_counts=True):
@@ -73,17 +90,14 @@ CASES = [
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"L{c[0]}_S{c[1]}")
-@pytest.mark.parametrize("route", ["auto", "tiled", "lds"])
+@pytest.mark.parametrize("route", ["auto", "tiled", "lds", "persistent"])
 def test_step_mcs_bit_exact(case, route):
     L, S, K, rates, n = case
-    if route == "tiled":
-        if L < 16:
-            pytest.skip("tiled path not used below L=16")
-        escg.set_single_lds_max_L(0)
-    elif route == "lds":
-        if L > escg.batch_max_L():
-            pytest.skip("lattice does not fit LDS")
-        escg.set_single_lds_max_L(100000)
+    if route in ("tiled", "persistent") and L < 16:
+        pytest.skip("tiled paths not used below L=16")
+    if route == "lds" and L > escg.batch_max_L(S):
+        pytest.skip("lattice does not fit LDS")
+    route_to(route)
     p, j = pair(L, S, K, *rates, seed=L * 7 + S, replica=3)
     g0 = random_lattice(L, S, seed=L, domain=3)
     mcs0 = 41
@@ -94,9 +108,9 @@ def test_step_mcs_bit_exact(case, route):
     assert np.array_equal(c, rc)
 
 
-@pytest.mark.parametrize("route", ["lds", "tiled"])
+@pytest.mark.parametrize("route", ["lds", "tiled", "persistent"])
 def test_zero_mcs_writes_only_row0(route):
-    escg.set_single_lds_max_L(100000 if route == "lds" else 0)
+    route_to(route)
     p, j = pair(64, 3, [1], 1.0)
     g0 = random_lattice(64, 3, seed=1)
     out, c = gpu_step(p, g0, 0, 0)
@@ -132,7 +146,9 @@ def test_workload_rps_L512_prefix():
     assert np.array_equal(host(cnt).reshape(rc.shape), rc)
 
 
-def test_workload_rpsls_L3200_prefix():
+@pytest.mark.parametrize("route", ["tiled", "persistent"])
+def test_workload_rpsls_L3200_prefix(route):
+    route_to(route)
     w = RPSLS3200
     n = 2
     p, j = pair(w.L, w.S, list(w.K), w.ex, w.sel, w.rep, seed=w.seed)
@@ -146,9 +162,9 @@ def test_workload_rpsls_L3200_prefix():
     assert np.array_equal(host(cnt).reshape(rc.shape), rc)
 
 
-@pytest.mark.parametrize("route", ["lds", "tiled"])
+@pytest.mark.parametrize("route", ["lds", "tiled", "persistent"])
 def test_resume_split_equals_straight(route):
-    escg.set_single_lds_max_L(100000 if route == "lds" else 0)
+    route_to(route)
     p, _ = pair(96, 5, [1, 3], 3.0, seed=5)
     g0 = random_lattice(96, 5, seed=3)
     a, ca = gpu_step(p, g0, 10, 9)
@@ -165,3 +181,20 @@ def test_exchange_only_is_a_permutation_large():
     out, c = gpu_step(p, g0, 0, 4)
     assert (c == c[0]).all()
     assert np.array_equal(np.sort(out), np.sort(g0))
+
+
+@pytest.mark.parametrize("L,S,K,ex,n", [(3200, 5, [1, 3], 51.2, 40),
+                                       (800, 3, [1], 64.0, 60),
+                                       (1600, 5, [1, 3], 12.8, 30)])
+def test_persistent_equals_per_mcs_tiled_long(L, S, K, ex, n):
+    """Many MCS at full size: the persistent kernel (halo exchange between
+    workgroups every MCS) against the per-MCS kernel, bytes and counts."""
+    p, _ = pair(L, S, K, ex, seed=11)
+    g0 = random_lattice(L, S, seed=5, domain=7)
+    route_to("persistent")
+    a, ca = gpu_step(p, g0, 100, n)
+    route_to("tiled")
+    b, cb = gpu_step(p, g0, 100, n)
+    assert np.array_equal(a, b)
+    assert np.array_equal(ca, cb)
+    assert (ca.sum(1) == L * L).all()
