@@ -188,6 +188,16 @@ escg_status escg_set_single_lds_max_L(uint32_t L_max);
  * MCS.  Same bytes either way.  Process-wide; always ESCG_OK. */
 escg_status escg_set_persistent_min_L(uint32_t L_min);
 
+/* Which kernel path the calling thread's last escg_step_mcs with n_mcs > 0
+ * enqueued: the whole lattice in one workgroup's LDS, one tiled launch per
+ * MCS, or the persistent tiled kernel (0 before any such call).  When the
+ * persistent path is planned but its cooperative launch is refused, the
+ * call falls back to per-MCS launches and escg_last_error() says why. */
+#define ESCG_ROUTE_LDS        1u
+#define ESCG_ROUTE_TILED      2u
+#define ESCG_ROUTE_PERSISTENT 3u
+uint32_t escg_last_route(void);
+
 /* Synchronises the current device and reports errors that asynchronous
  * kernels can only record on the device: ESCG_ETIMEOUT if a persistent
  * kernel abandoned a bounded wait for a neighbouring workgroup since the

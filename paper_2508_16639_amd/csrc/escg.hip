@@ -521,6 +521,55 @@ __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
         tile_store(lat, a.lattice, G, ty, tx);
 }
 
+// One MCS of a large lattice per launch with the tile phases above: each
+// workgroup loads its tile and halo from `src`, runs the four passes and
+// stores the interior to `dst`.  No waits between workgroups, so launches can
+// share the GPU with other work.
+struct StepArgs {
+    const uint8_t *src;
+    uint8_t *dst;
+    uint32_t *counts; // this MCS's row (S+1, zeroed) or null
+    uint64_t seed;
+    TileGeom G;
+    uint32_t S, T1, T2, replica, t;
+    uint32_t dom[32];
+};
+
+template <bool kPacked>
+__global__ __launch_bounds__(512) void tiled_step_kernel(StepArgs a)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint32_t *s_dom = reinterpret_cast<uint32_t *>(smem + kOffDom);
+    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(smem + kOffCnt);
+    uint8_t *lat = smem + lattice_lds_offset(a.S);
+    const TileGeom G = a.G;
+    const uint32_t tid = threadIdx.x, S = a.S;
+    const uint32_t ty = blockIdx.x / G.TX, tx = blockIdx.x - ty * G.TX;
+    if (tid < 32) {
+        s_dom[tid] = a.dom[tid];
+        s_cnt[tid] = 0;
+    }
+    tile_load(lat, a.src, G, ty, tx);
+    __syncthreads();
+    build_quad_luts(reinterpret_cast<uint2 *>(smem + kOffSel),
+                    reinterpret_cast<uint16_t *>(smem + kOffRule),
+                    species_pow2(S), s_dom);
+    __syncthreads();
+    const QuadCtx qc = make_quad_ctx(smem, S, a.T1, a.T2);
+    tile_mcs(lat, G, ty, tx, a.t, a.replica, (uint32_t)a.seed,
+             (uint32_t)(a.seed >> 32), qc);
+    tile_store(lat, a.dst, G, ty, tx);
+    if (a.counts) {
+        if (kPacked)
+            tile_count<8>(lat, G, S, s_cnt);
+        else
+            tile_count<32>(lat, G, S, s_cnt);
+        __syncthreads();
+        if (tid <= S && s_cnt[tid])
+            atomicAdd(&a.counts[tid], s_cnt[tid]);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Small kernels
 // ---------------------------------------------------------------------------
@@ -714,6 +763,7 @@ uint32_t lds_max_L(uint32_t S)
 std::atomic<uint32_t> g_single_lds_max_L{192};
 
 thread_local char g_last_error[160] = "";
+thread_local uint32_t g_last_route = 0;
 
 escg_status last_hip(hipError_t e)
 {
@@ -923,6 +973,67 @@ TiledPlan plan_tiled(uint32_t L, uint32_t S)
     return plan;
 }
 
+// Tile geometry for the per-MCS kernel: equal tiles dividing L, TW % 8 == 0,
+// TH even >= 4; no residency requirement.  Cost: halo-inflated area over
+// the whole grid plus a per-tile launch charge, assuming the tiles spread
+// evenly over the CUs.
+TiledPlan plan_step_uncached(uint32_t L, uint32_t S)
+{
+    TiledPlan best;
+    if (L % 8 != 0 || L < 16)
+        return best;
+    const DeviceInfo di = device_info();
+    const double cus = std::max(1, di.cus);
+    const size_t lds_max = di.lds_max ? di.lds_max : 65536;
+    double best_cost = 1e300;
+    for (uint32_t TW = 8; TW <= L && TW <= 512; TW += 8) {
+        if (L % TW)
+            continue;
+        for (uint32_t TH = 4; TH <= L && TH <= 512; TH += 2) {
+            if (L % TH)
+                continue;
+            TileGeom G{L, TH, TW, L / TH, L / TW};
+            const size_t lds = (size_t)lattice_lds_offset(S) +
+                               G.region_bytes() + 64;
+            if (lds > lds_max)
+                continue;
+            const double T = (double)G.TY * G.TX;
+            const double area = (double)(TH + 8) * (TW + 16);
+            // work per CU, rounded up to whole tiles, plus a fixed cost per
+            // tile for the load / table setup / store
+            const double waves = std::ceil(T / (2.0 * cus));
+            const double cost = waves * 2.0 * (area + 3000.0);
+            if (cost < best_cost) {
+                best_cost = cost;
+                best.ok = true;
+                best.G = G;
+                best.threads = std::min(512u, tiled_threads(G));
+                best.lds = lds;
+            }
+        }
+    }
+    return best;
+}
+
+TiledPlan plan_step(uint32_t L, uint32_t S)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, uint32_t, bool>, TiledPlan> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const auto key = std::make_tuple(dev, L, S <= 7);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end())
+            return it->second;
+    }
+    const TiledPlan plan = plan_step_uncached(L, S <= 7 ? 7u : 31u);
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = plan;
+    return plan;
+}
+
 // Runs n_mcs MCS of a large lattice with the persistent kernel.  Returns
 // ESCG_EUNSUPPORTED (nothing enqueued) if no plan fits or the cooperative
 // launch is refused; the caller then uses the per-MCS tiled kernel.
@@ -971,6 +1082,9 @@ escg_status run_tiled_persistent(const escg_params *p, const Derived &d,
                                               args, (unsigned)plan.lds, st);
     escg_status s = ESCG_OK;
     if (e != hipSuccess) {
+        std::snprintf(g_last_error, sizeof(g_last_error),
+                      "cooperative launch of %u x %u refused: %s", T,
+                      plan.threads, hipGetErrorName(e));
         (void)hipGetLastError();
         s = ESCG_EUNSUPPORTED;
     }
@@ -1090,6 +1204,7 @@ escg_status escg_step_mcs(const escg_params *p, uint8_t *d_lattice,
     if (L <= std::min(g_single_lds_max_L.load(), lds_max_L(S))) {
         JobDev J = make_job(p, d, 0, mcs0, n_mcs, ESCG_STOP_NONE, 0, d_counts,
                             nullptr, 0);
+        g_last_route = ESCG_ROUTE_LDS;
         return launch_lds_single(J, d.small, d_lattice, st);
     }
     if (d_counts) {
@@ -1102,22 +1217,58 @@ escg_status escg_step_mcs(const escg_params *p, uint8_t *d_lattice,
         return ESCG_OK;
     if (L >= g_tiled_min_L.load()) {
         s = run_tiled_persistent(p, d, d_lattice, mcs0, n_mcs, d_counts, st);
-        if (s != ESCG_EUNSUPPORTED)
+        if (s != ESCG_EUNSUPPORTED) {
+            g_last_route = ESCG_ROUTE_PERSISTENT;
             return s;
+        }
         s = ESCG_OK;
     }
+    g_last_route = ESCG_ROUTE_TILED;
     uint8_t *other = nullptr;
     if (hipMallocAsync((void **)&other, N, st) != hipSuccess)
         return ESCG_ENOMEM;
-    TileArgs a = tile_args(p, d);
     uint8_t *cur = d_lattice, *nxt = other;
-    for (uint32_t k = 0; k < n_mcs; ++k) {
-        a.src = cur;
-        a.dst = nxt;
-        a.t = mcs0 + k;
-        a.counts = d_counts ? d_counts + (size_t)(k + 1) * (S + 1) : nullptr;
-        launch_tile_mcs(a, d.small, st);
-        std::swap(cur, nxt);
+    const TiledPlan sp = plan_step(L, S);
+    if (sp.ok) {
+        StepArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.seed = p->seed;
+        a.G = sp.G;
+        a.S = S;
+        a.T1 = d.T1;
+        a.T2 = d.T2;
+        a.replica = p->replica;
+        for (int i = 0; i < 32; ++i)
+            a.dom[i] = p->dom[i];
+        const void *fn = d.small ? (const void *)tiled_step_kernel<true>
+                                 : (const void *)tiled_step_kernel<false>;
+        allow_dynamic_lds(fn, sp.lds);
+        const uint32_t T = sp.G.TY * sp.G.TX;
+        for (uint32_t k = 0; k < n_mcs; ++k) {
+            a.src = cur;
+            a.dst = nxt;
+            a.t = mcs0 + k;
+            a.counts =
+                d_counts ? d_counts + (size_t)(k + 1) * (S + 1) : nullptr;
+            if (d.small)
+                hipLaunchKernelGGL(tiled_step_kernel<true>, dim3(T),
+                                   dim3(sp.threads), sp.lds, st, a);
+            else
+                hipLaunchKernelGGL(tiled_step_kernel<false>, dim3(T),
+                                   dim3(sp.threads), sp.lds, st, a);
+            std::swap(cur, nxt);
+        }
+    } else {
+        TileArgs a = tile_args(p, d);
+        for (uint32_t k = 0; k < n_mcs; ++k) {
+            a.src = cur;
+            a.dst = nxt;
+            a.t = mcs0 + k;
+            a.counts =
+                d_counts ? d_counts + (size_t)(k + 1) * (S + 1) : nullptr;
+            launch_tile_mcs(a, d.small, st);
+            std::swap(cur, nxt);
+        }
     }
     if (cur != d_lattice)
         launch_copy(d_lattice, cur, N, st);
@@ -1207,6 +1358,8 @@ escg_status escg_set_single_lds_max_L(uint32_t L)
     g_single_lds_max_L = L;
     return ESCG_OK;
 }
+
+uint32_t escg_last_route(void) { return g_last_route; }
 
 escg_status escg_set_persistent_min_L(uint32_t L)
 {

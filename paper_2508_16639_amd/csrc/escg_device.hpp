@@ -72,9 +72,11 @@ __device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1,
 
 __device__ __forceinline__ uint32_t pick(const Words &q, uint32_t i)
 {
-    // i in 0..3; selects without dynamic register indexing
-    const uint32_t lo = (i & 1u) ? q.w[1] : q.w[0];
-    const uint32_t hi = (i & 1u) ? q.w[3] : q.w[2];
+    // i in 0..3; selects between values (not lvalues, whose ?: would select
+    // addresses and force the words into scratch memory)
+    const uint32_t w0 = q.w[0], w1 = q.w[1], w2 = q.w[2], w3 = q.w[3];
+    const uint32_t lo = (i & 1u) ? w1 : w0;
+    const uint32_t hi = (i & 1u) ? w3 : w2;
     return (i & 2u) ? hi : lo;
 }
 

@@ -105,7 +105,11 @@ __device__ __forceinline__ uint32_t block_update(uint32_t B, uint32_t w,
 {
     const uint2 s = c.sel[w & 0xFFu];
     const uint32_t xy = perm(B, B, s.x);
-    const uint32_t base = (w <= c.W1) ? c.B1 : ((w <= c.W2) ? c.B2 : c.B3);
+    // select values, not lvalues (an lvalue ?: selects addresses and keeps
+    // the context in scratch memory)
+    const uint32_t b1 = c.B1, b2 = c.B2, b3 = c.B3;
+    uint32_t base = (w <= c.W2) ? b2 : b3;
+    base = (w <= c.W1) ? b1 : base;
     const uint32_t off = __builtin_amdgcn_udot4(xy, c.dotw, base, false);
     const uint32_t out = *reinterpret_cast<const uint16_t *>(c.rule + off);
     return perm(out, B, s.y);

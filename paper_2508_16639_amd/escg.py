@@ -19,6 +19,8 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)),
                          "libescg.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ETIMEOUT = 0, -1, -2, -3, -4, -5
+ROUTE_LDS, ROUTE_TILED, ROUTE_PERSISTENT = 1, 2, 3
+ROUTE_NAMES = {0: "none", 1: "lds", 2: "tiled", 3: "persistent"}
 STOP_FIRST_EXTINCTION, STOP_MONOCULTURE, STOP_NONE = 0, 1, 2
 BATCH_RESULT_WORDS = 34
 MAX_SPECIES = 31
@@ -45,7 +47,7 @@ EXPORTS = ("escg_status_str", "escg_last_error", "escg_circulant_dom", "escg_dom
            "escg_thresholds", "escg_init", "escg_densities", "escg_step_mcs",
            "escg_run_until_extinction", "escg_batch_max_L", "escg_batch_run",
            "escg_set_single_lds_max_L", "escg_set_persistent_min_L",
-           "escg_async_status")
+           "escg_async_status", "escg_last_route")
 
 _lib = None
 
@@ -86,9 +88,11 @@ def lib():
     L.escg_set_single_lds_max_L.argtypes = [u32]
     L.escg_set_persistent_min_L.argtypes = [u32]
     L.escg_async_status.argtypes = [C.c_int]
+    L.escg_last_route.argtypes = []
+    L.escg_last_route.restype = u32
     for name in EXPORTS:
         if name not in ("escg_status_str", "escg_batch_max_L",
-                        "escg_last_error"):
+                        "escg_last_error", "escg_last_route"):
             getattr(L, name).restype = C.c_int32
     _lib = L
     return L
@@ -167,6 +171,16 @@ def batch_max_L(S: int = 3) -> int:
 def set_persistent_min_L(L: int) -> None:
     _check(lib().escg_set_persistent_min_L(int(L)),
            "escg_set_persistent_min_L")
+
+
+def last_route() -> str:
+    """Path taken by this thread's last step_mcs ("lds", "tiled",
+    "persistent")."""
+    return ROUTE_NAMES[int(lib().escg_last_route())]
+
+
+def last_error() -> str:
+    return lib().escg_last_error().decode()
 
 
 def async_status(reset: bool = True) -> None:

@@ -1,0 +1,337 @@
+"""Continuous-batching job server for ESCG simulations on one GPU.
+
+Requests (lattice side L, species S with circulant dominance K, mobility,
+MCS budget, seed) arrive over time.  The scheduler admits queued jobs in
+arrival order while the job's device footprint fits the HBM budget and a
+slot is free, keeps every admitted job's lattice resident on the device,
+and runs iterations: each iteration advances every active job by a chunk of
+MCS sized to a common amount of work, then retires finished jobs.  Jobs that
+arrive while an iteration runs join at the next iteration boundary.
+
+Work within an iteration overlaps on the device: all active jobs small
+enough for one workgroup's LDS advance together in one persistent batched
+launch (one workgroup per job), while larger jobs advance with per-MCS tiled
+launches on their own streams at the same time.  Because every random draw
+is keyed by (seed, replica, MCS, pass, site), a job's result does not depend
+on its co-runners, on chunking or on admission time: it is byte-identical to
+the job run alone.
+
+The executor interface (alloc / advance / collect / free) keeps the
+scheduler testable with a CPU executor and an injected clock.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+from typing import Callable, Dict, List, Optional
+
+import numpy as np
+
+
+@dataclass
+class JobState:
+    req: object                    # workloads.Request
+    done_mcs: int = 0
+    t_admit: float = float("nan")
+    t_done: float = float("nan")
+    handle: object = None          # executor-owned device state
+    result: Optional[np.ndarray] = None  # final counts[0..S]
+    failed: str = ""
+
+    @property
+    def footprint(self) -> int:
+        return footprint_bytes(self.req.L)
+
+
+def footprint_bytes(L: int) -> int:
+    """Device bytes a job holds while admitted: its lattice plus the
+    ping-pong lattice of the per-MCS tiled path."""
+    return 2 * L * L + 4096
+
+
+@dataclass
+class ServerConfig:
+    hbm_budget: int = 64 << 30     # bytes of device memory for job state
+    max_active: int = 512          # slots
+    work_per_iter: float = 4e8     # site-updates per job per iteration
+    min_chunk: int = 8             # MCS
+    max_chunk: int = 2000          # MCS
+
+
+@dataclass
+class Stats:
+    latencies: List[float] = field(default_factory=list)
+    completed: int = 0
+    failed: int = 0
+    iterations: int = 0
+    peak_active: int = 0
+    peak_footprint: int = 0
+    site_updates: float = 0.0
+    wall: float = 0.0
+
+    def summary(self) -> Dict[str, float]:
+        lat = np.asarray(self.latencies) if self.latencies else np.zeros(1)
+        return {
+            "completed": self.completed,
+            "failed": self.failed,
+            "jobs_per_s": self.completed / self.wall if self.wall else 0.0,
+            "site_updates_per_s": self.site_updates / self.wall
+            if self.wall else 0.0,
+            "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)),
+            "mean_latency_s": float(lat.mean()),
+            "iterations": self.iterations,
+            "peak_active": self.peak_active,
+            "peak_footprint_bytes": self.peak_footprint,
+            "wall_s": self.wall,
+        }
+
+
+class Scheduler:
+    """Admission, iteration and retirement; device work goes through the
+    executor.  `clock()` returns seconds; arrivals are relative to the start
+    of run()."""
+
+    def __init__(self, executor, config: ServerConfig = ServerConfig(),
+                 clock: Callable[[], float] = time.perf_counter,
+                 sleep: Callable[[float], None] = time.sleep):
+        self.ex = executor
+        self.cfg = config
+        self.clock = clock
+        self.sleep = sleep
+
+    def chunk_for(self, job: JobState) -> int:
+        L2 = float(job.req.L) ** 2
+        c = int(self.cfg.work_per_iter / L2)
+        c = max(self.cfg.min_chunk, min(self.cfg.max_chunk, c))
+        return min(c, job.req.mcs - job.done_mcs)
+
+    def run(self, requests) -> (Stats, Dict[int, JobState]):
+        reqs = sorted(requests, key=lambda r: r.arrival_s)
+        pending = deque(reqs)
+        queue: deque = deque()
+        active: List[JobState] = []
+        jobs: Dict[int, JobState] = {}
+        st = Stats()
+        used = 0
+        t0 = self.clock()
+        while pending or queue or active:
+            now = self.clock() - t0
+            while pending and pending[0].arrival_s <= now:
+                r = pending.popleft()
+                js = JobState(req=r)
+                jobs[r.job_id] = js
+                queue.append(js)
+            # admission: arrival order, no overtaking
+            while queue and len(active) < self.cfg.max_active:
+                js = queue[0]
+                if js.footprint > self.cfg.hbm_budget:
+                    queue.popleft()
+                    js.failed = "footprint exceeds the HBM budget"
+                    st.failed += 1
+                    continue
+                if used + js.footprint > self.cfg.hbm_budget:
+                    break
+                queue.popleft()
+                try:
+                    js.handle = self.ex.alloc(js.req)
+                except Exception as e:  # invalid job: isolate it
+                    js.failed = f"rejected: {e}"
+                    st.failed += 1
+                    continue
+                js.t_admit = self.clock() - t0
+                used += js.footprint
+                active.append(js)
+            st.peak_active = max(st.peak_active, len(active))
+            st.peak_footprint = max(st.peak_footprint, used)
+            if not active:
+                if pending:
+                    wait = pending[0].arrival_s - (self.clock() - t0)
+                    if wait > 0:
+                        self.sleep(wait)
+                continue
+            work = [(js, self.chunk_for(js)) for js in active]
+            try:
+                self.ex.advance([(js.handle, js.req, js.done_mcs, n)
+                                 for js, n in work])
+            except Exception as e:  # executor failure: fail this iteration's
+                for js, _ in work:  # jobs, keep serving the others
+                    js.failed = f"executor: {e}"
+                    st.failed += 1
+                    self.ex.free(js.handle)
+                    used -= js.footprint
+                active = []
+                continue
+            st.iterations += 1
+            still = []
+            for js, n in work:
+                js.done_mcs += n
+                st.site_updates += float(js.req.L) ** 2 * n
+                if js.done_mcs >= js.req.mcs:
+                    js.result = self.ex.collect(js.handle, js.req)
+                    js.t_done = self.clock() - t0
+                    st.latencies.append(js.t_done - js.req.arrival_s)
+                    st.completed += 1
+                    self.ex.free(js.handle)
+                    used -= js.footprint
+                else:
+                    still.append(js)
+            active = still
+        st.wall = self.clock() - t0
+        return st, jobs
+
+
+class DeviceExecutor:
+    """Runs jobs on the current GPU through the C ABI."""
+
+    def __init__(self, torch, escg, n_streams: int = 4,
+                 keep_lattices: bool = False):
+        self.torch = torch
+        self.escg = escg
+        self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        self.batch_stream = torch.cuda.Stream()
+        self.small_max = {}
+        self.keep = keep_lattices
+        self.final_lattices: Dict[int, np.ndarray] = {}
+
+    def _params(self, req):
+        return self.escg.Params(L=req.L, S=req.S,
+                                dom=self.escg.circulant_dom(req.S, req.K),
+                                ex=req.ex, sel=1.0, rep=1.0, seed=req.seed,
+                                replica=0)
+
+    def is_small(self, req) -> bool:
+        if req.S not in self.small_max:
+            self.small_max[req.S] = self.escg.batch_max_L(req.S)
+        return req.L <= self.small_max[req.S]
+
+    def alloc(self, req):
+        p = self._params(req)
+        self.escg.thresholds(p)  # validates rates
+        lat = self.torch.empty(req.L * req.L, dtype=self.torch.uint8,
+                               device="cuda")
+        self.escg.init(p, lat)  # current stream; work streams wait on it
+        return {"p": p, "lat": lat}
+
+    def advance(self, work):
+        torch, escg = self.torch, self.escg
+        small = [(h, r, m0, n) for h, r, m0, n in work if self.is_small(r)]
+        large = [(h, r, m0, n) for h, r, m0, n in work if not self.is_small(r)]
+        cur = torch.cuda.current_stream()
+        done = []
+        self.batch_stream.wait_stream(cur)
+        for s in self.streams:
+            s.wait_stream(cur)
+        if small:
+            # one persistent launch for all small jobs; lattices live in
+            # separate tensors, so pass offsets from the lowest address
+            base = min(h["lat"].data_ptr() for h, _, _, _ in small)
+            top = max(h["lat"].data_ptr() + r.L * r.L for h, r, _, _ in small)
+            view = _DevView(base, top - base)
+            offs = [h["lat"].data_ptr() - base for h, _, _, _ in small]
+            res = torch.empty(len(small) * escg.BATCH_RESULT_WORDS,
+                              dtype=torch.int32, device="cuda")
+            with torch.cuda.stream(self.batch_stream):
+                escg.batch_run([h["p"] for h, _, _, _ in small], offs, view,
+                               [n for _, _, _, n in small],
+                               escg.STOP_NONE, False, res,
+                               mcs0=[m0 for _, _, m0, _ in small])
+                ev = torch.cuda.Event()
+                ev.record()
+                done.append(ev)
+            self._res = res  # alive until the iteration completes
+        for i, (h, r, m0, n) in enumerate(large):
+            s = self.streams[i % len(self.streams)]
+            with torch.cuda.stream(s):
+                escg.step_mcs(h["p"], h["lat"], m0, n, None)
+                ev = torch.cuda.Event()
+                ev.record()
+                done.append(ev)
+        for ev in done:
+            cur.wait_event(ev)
+        cur.synchronize()
+
+    def collect(self, h, req):
+        cnt = self.torch.empty(req.S + 1, dtype=self.torch.int32,
+                               device="cuda")
+        self.escg.densities(h["p"], h["lat"], cnt)
+        if self.keep:
+            self.final_lattices[req.job_id] = h["lat"].cpu().numpy().copy()
+        return cnt.cpu().numpy().view(np.uint32).copy()
+
+    def free(self, h):
+        h.clear()
+
+
+class _DevView:
+    """A raw device span presented to escg.batch_run as a uint8 tensor-like
+    object (pointer + size); the spans of the jobs inside are disjoint
+    tensors owned by the executor."""
+
+    def __init__(self, ptr: int, nbytes: int):
+        import torch
+        self._ptr = ptr
+        self._n = nbytes
+        self.is_cuda = True
+        self.dtype = torch.uint8
+
+    def data_ptr(self):
+        return self._ptr
+
+    def numel(self):
+        return self._n
+
+    def is_contiguous(self):
+        return True
+
+
+def plain_serving(torch, escg, requests, clock=time.perf_counter,
+                  sleep=time.sleep):
+    """Baseline: one job at a time in arrival order, each with the best
+    single-job path (init, all MCS, counts, synchronise)."""
+    st = Stats()
+    t0 = clock()
+    for r in sorted(requests, key=lambda r: r.arrival_s):
+        now = clock() - t0
+        if r.arrival_s > now:
+            sleep(r.arrival_s - now)
+        p = escg.Params(L=r.L, S=r.S, dom=escg.circulant_dom(r.S, r.K),
+                        ex=r.ex, seed=r.seed)
+        lat = torch.empty(r.L * r.L, dtype=torch.uint8, device="cuda")
+        cnt = torch.empty(r.S + 1, dtype=torch.int32, device="cuda")
+        escg.init(p, lat)
+        escg.step_mcs(p, lat, 0, r.mcs, None)
+        escg.densities(p, lat, cnt)
+        torch.cuda.synchronize()
+        st.latencies.append(clock() - t0 - r.arrival_s)
+        st.completed += 1
+        st.site_updates += float(r.L) ** 2 * r.mcs
+    st.wall = clock() - t0
+    return st
+
+
+def bench_serving(torch, escg, workloads, n_jobs: int = 2000):
+    """The Poisson serving workload through the server and through plain
+    one-at-a-time serving, on the same GPU."""
+    reqs = workloads.serving_requests(n=n_jobs)
+    ex = DeviceExecutor(torch, escg)
+    # large jobs share the GPU with the batch: per-MCS tiled launches
+    escg.set_persistent_min_L(1 << 30)
+    try:
+        st, _ = Scheduler(ex).run(reqs)
+    finally:
+        escg.set_persistent_min_L(400)
+    escg.async_status()
+    plain = plain_serving(torch, escg, reqs)
+    s = st.summary()
+    pl = plain.summary()
+    return {
+        "workload": f"{n_jobs} jobs, Poisson 200/s, S in {{3,5}}, "
+                    "L in {100,200,400,800,1600}, M log-uniform [1e-6,1e-3], "
+                    "MCS uniform [500,5000]",
+        "server": s,
+        "plain": pl,
+        "speedup_jobs_per_s": s["jobs_per_s"] / pl["jobs_per_s"]
+        if pl["jobs_per_s"] else None,
+    }

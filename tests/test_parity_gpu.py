@@ -39,11 +39,20 @@ def _default_routing():
     escg.async_status()
 
 
-def gpu_step(p, g0, mcs0, n, want_counts=True):
+EXPECT_ROUTE = {"auto": None}
+
+
+def gpu_step(p, g0, mcs0, n, want_counts=True, route=None):
     lat = dev(g0)
     cnt = (torch.full(((n + 1) * (p.S + 1),), -1, dtype=torch.int32,
                       device="cuda:0") if want_counts else None)
     escg.step_mcs(p, lat, mcs0, n, cnt)
+    if route not in (None, "auto") and n > 0:
+        got = escg.last_route()
+        if route == "persistent" and p.L % 8:
+            assert got == "tiled", got          # persistent needs L % 8 == 0
+        else:
+            assert got == route, (got, escg.last_error())
     out = host(lat)
     c = host(cnt).reshape(n + 1, p.S + 1) if want_counts else None
     return out, c
@@ -101,7 +110,7 @@ def test_step_mcs_bit_exact(case, route):
     p, j = pair(L, S, K, *rates, seed=L * 7 + S, replica=3)
     g0 = random_lattice(L, S, seed=L, domain=3)
     mcs0 = 41
-    out, c = gpu_step(p, g0, mcs0, n)
+    out, c = gpu_step(p, g0, mcs0, n, route=route)
     ref = g0.copy()
     rc = O.o2_run(j, ref, mcs0, n)
     assert np.array_equal(out, ref)
@@ -156,6 +165,8 @@ def test_workload_rpsls_L3200_prefix(route):
     escg.init(p, lat)
     cnt = torch.empty((n + 1) * (w.S + 1), dtype=torch.int32, device="cuda:0")
     escg.step_mcs(p, lat, 0, n, cnt)
+    if w.L == 3200:
+        assert escg.last_route() == route, escg.last_error()
     g = j.init()
     rc = O.o2_run(j, g, 0, n)
     assert np.array_equal(host(lat), g)
@@ -192,9 +203,9 @@ def test_persistent_equals_per_mcs_tiled_long(L, S, K, ex, n):
     p, _ = pair(L, S, K, ex, seed=11)
     g0 = random_lattice(L, S, seed=5, domain=7)
     route_to("persistent")
-    a, ca = gpu_step(p, g0, 100, n)
+    a, ca = gpu_step(p, g0, 100, n, route="persistent")
     route_to("tiled")
-    b, cb = gpu_step(p, g0, 100, n)
+    b, cb = gpu_step(p, g0, 100, n, route="tiled")
     assert np.array_equal(a, b)
     assert np.array_equal(ca, cb)
     assert (ca.sum(1) == L * L).all()
