@@ -467,11 +467,13 @@ __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
         tile_mcs(lat, G, ty, tx, a.mcs0 + t, a.replica, k0, k1, qc);
         const uint32_t slot = (t + 1) & 1u;
         tile_publish(lat, a.exch + (size_t)(2 * tile + slot) * sd, G);
-        // the strips must have reached L2 before the flag is released
+        // every wave's strip stores (sc1, device-coherent) must have
+        // completed before the flag announces them; no cache maintenance
+        // is needed because neither side caches the exchange area
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (tid == 0)
-            __hip_atomic_store(&a.flags[tile], t + 1, __ATOMIC_RELEASE,
+            __hip_atomic_store(&a.flags[tile], t + 1, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         if (a.counts) {
             if (kPacked)
@@ -485,17 +487,20 @@ __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
             const uint32_t ny = (ty + G.TY + dy - 1) % G.TY;
             const uint32_t nx = (tx + G.TX + dx - 1) % G.TX;
             const uint32_t *f = &a.flags[ny * G.TX + nx];
+            // relaxed sc1 polls; the barrier below orders the strip loads
             uint32_t spins = 0;
-            while (__hip_atomic_load(f, __ATOMIC_ACQUIRE,
+            while (__hip_atomic_load(f, __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_AGENT) < t + 1) {
-                if (__hip_atomic_load(a.abort, __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT))
-                    break;
-                if (++spins > a.spin_limit) {
-                    __hip_atomic_store(a.abort, 1u, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                    atomicOr(&g_async_error, 1u);
-                    break;
+                if ((++spins & 63u) == 0) {
+                    if (__hip_atomic_load(a.abort, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT))
+                        break;
+                    if (spins > a.spin_limit) {
+                        __hip_atomic_store(a.abort, 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        atomicOr(&g_async_error, 1u);
+                        break;
+                    }
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
@@ -513,8 +518,7 @@ __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
             aborted = true;
             break;
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        tile_gather(lat, a.exch, G, ty, tx, slot);
+        tile_gather(lat, a.exch, G, ty, tx, slot); // sc1 loads
         __syncthreads();
     }
     if (!aborted)
@@ -1068,7 +1072,7 @@ escg_status run_tiled_persistent(const escg_params *p, const Derived &d,
     a.replica = p->replica;
     a.mcs0 = mcs0;
     a.n_mcs = n_mcs;
-    a.spin_limit = 4000000u;
+    a.spin_limit = 1u << 26; // polls (~seconds), then abort with an error
     for (int i = 0; i < 32; ++i)
         a.dom[i] = p->dom[i];
     launch_fill(a.flags, T + 64, 0, st);

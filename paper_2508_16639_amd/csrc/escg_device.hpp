@@ -46,29 +46,58 @@ struct Words {
     uint32_t w[4];
 };
 
-// Ten Philox rounds.  Counter words that are uniform across the wave (MCS
-// index, tag, replica) stay in scalar registers through the first rounds.
+// a ^ b ^ k in one gfx950 instruction (v_bitop3_b32 with truth table 0x96);
+// k must be wave-uniform (it is read from a scalar register).
+__device__ __forceinline__ uint32_t xor3_vvs(uint32_t a, uint32_t b,
+                                             uint32_t k)
+{
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96"
+        : "=v"(r)
+        : "v"(a), "v"(b), "s"(k));
+    return r;
+}
+
+// One Philox round: (c0, c1, c2, c3) with round key (k0, k1).
+#define ESCG_PHILOX_ROUND(X0, X1)                                             \
+    do {                                                                      \
+        const uint64_t pa = (uint64_t)kMulA * c0;                             \
+        const uint64_t pb = (uint64_t)kMulB * c2;                             \
+        const uint32_t n0 = X0((uint32_t)(pb >> 32), c1, k0);                 \
+        const uint32_t n2 = X1((uint32_t)(pa >> 32), c3, k1);                 \
+        c1 = (uint32_t)pb;                                                    \
+        c3 = (uint32_t)pa;                                                    \
+        c0 = n0;                                                              \
+        c2 = n2;                                                              \
+        k0 += kWeylA;                                                         \
+        k1 += kWeylB;                                                         \
+    } while (0)
+
+__device__ __forceinline__ uint32_t xor3_c(uint32_t a, uint32_t b, uint32_t k)
+{
+    return a ^ b ^ k;
+}
+
+// Ten Philox rounds for a counter whose word c0 varies across the wave and
+// whose words c1..c3 and key are wave-uniform (all callers here).  The first
+// rounds are written in C so the compiler keeps their uniform parts in
+// scalar registers; from the point where both XOR inputs of a word vary
+// across lanes, the three-way XOR is one v_bitop3 instead of two v_xor.
 __device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1,
                                           uint32_t c2, uint32_t c3,
                                           uint32_t k0, uint32_t k1)
 {
+    ESCG_PHILOX_ROUND(xor3_c, xor3_c);   // c0 varies; c1..c3 uniform
+    ESCG_PHILOX_ROUND(xor3_c, xor3_c);   // c2, c3 vary; c0, c1 uniform
+    ESCG_PHILOX_ROUND(xor3_vvs, xor3_c); // c0, c1, c2 vary; c3 uniform
 #pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t pa = (uint64_t)kMulA * c0;
-        const uint64_t pb = (uint64_t)kMulB * c2;
-        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
-        c1 = (uint32_t)pb;
-        c3 = (uint32_t)pa;
-        c0 = n0;
-        c2 = n2;
-        k0 += kWeylA;
-        k1 += kWeylB;
-    }
+    for (int r = 3; r < 10; ++r)
+        ESCG_PHILOX_ROUND(xor3_vvs, xor3_vvs);
     Words o;
     o.w[0] = c0; o.w[1] = c1; o.w[2] = c2; o.w[3] = c3;
     return o;
 }
+#undef ESCG_PHILOX_ROUND
 
 __device__ __forceinline__ uint32_t pick(const Words &q, uint32_t i)
 {

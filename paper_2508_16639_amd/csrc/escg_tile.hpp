@@ -112,6 +112,19 @@ __device__ __forceinline__ void tile_mcs(uint8_t *lat, const TileGeom &G,
     }
 }
 
+// Device-coherent word store / load for the exchange area: relaxed
+// agent-scope atomics compile to sc1 stores and loads, which are coherent
+// across XCDs without L2 writeback or invalidation.
+__device__ __forceinline__ void xstore(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t xload(const uint32_t *p)
+{
+    return __hip_atomic_load(const_cast<uint32_t *>(p), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Writes the interior's border strips into exchange slot `slot`.
 __device__ inline void tile_publish(const uint8_t *lat, uint32_t *slot,
                                     const TileGeom &G)
@@ -121,17 +134,17 @@ __device__ inline void tile_publish(const uint8_t *lat, uint32_t *slot,
              *right = left + 2 * TH;
     for (uint32_t i = threadIdx.x; i < 4 * dwr; i += blockDim.x) {
         const uint32_t r = i / dwr, j = i - r * dwr;
-        top[i] = *reinterpret_cast<const uint32_t *>(lat + (4 + r) * LS + 8 +
-                                                     4 * j);
-        bot[i] = *reinterpret_cast<const uint32_t *>(lat + (TH + r) * LS + 8 +
-                                                     4 * j);
+        xstore(top + i, *reinterpret_cast<const uint32_t *>(
+                            lat + (4 + r) * LS + 8 + 4 * j));
+        xstore(bot + i, *reinterpret_cast<const uint32_t *>(
+                            lat + (TH + r) * LS + 8 + 4 * j));
     }
     for (uint32_t i = threadIdx.x; i < 2 * TH; i += blockDim.x) {
         const uint32_t r = i >> 1, j = i & 1u;
-        left[i] = *reinterpret_cast<const uint32_t *>(lat + (4 + r) * LS + 8 +
-                                                      4 * j);
-        right[i] = *reinterpret_cast<const uint32_t *>(lat + (4 + r) * LS +
-                                                       TW + 4 * j);
+        xstore(left + i, *reinterpret_cast<const uint32_t *>(
+                             lat + (4 + r) * LS + 8 + 4 * j));
+        xstore(right + i, *reinterpret_cast<const uint32_t *>(
+                              lat + (4 + r) * LS + TW + 4 * j));
     }
 }
 
@@ -162,21 +175,22 @@ __device__ inline void tile_gather(uint8_t *lat, const uint32_t *nb,
         const uint32_t *mid = topside ? sU + TW : sD;      // bottom / top strip
         const uint32_t *lft = topside ? sUL + TW : sDL;
         const uint32_t *rgt = topside ? sUR + TW : sDR;
-        uint32_t v;
+        const uint32_t *src;
         if (j < 2)
-            v = lft[r * dwr + dwr - 2 + j];
+            src = lft + r * dwr + dwr - 2 + j;
         else if (j < dwr + 2)
-            v = mid[r * dwr + j - 2];
+            src = mid + r * dwr + j - 2;
         else
-            v = rgt[r * dwr + j - 2 - dwr];
+            src = rgt + r * dwr + j - 2 - dwr;
+        const uint32_t v = xload(src);
         *reinterpret_cast<uint32_t *>(lat + lr * LS + 4 * j) = v;
     }
     // columns 0..7 and TW+8..TW+15 of rows 4..TH+3 from the side strips
     for (uint32_t i = threadIdx.x; i < 4 * TH; i += blockDim.x) {
         const uint32_t side = i / (2 * TH), q = i - side * 2 * TH;
         const uint32_t r = q >> 1, j = q & 1u;
-        const uint32_t v = side == 0 ? (sL + 2 * TW + 2 * TH)[q]   // right strip
-                                     : (sR + 2 * TW)[q];            // left strip
+        const uint32_t v = xload(side == 0 ? sL + 2 * TW + 2 * TH + q // right
+                                           : sR + 2 * TW + q);         // left
         const uint32_t c = side == 0 ? 4 * j : TW + 8 + 4 * j;
         *reinterpret_cast<uint32_t *>(lat + (4 + r) * LS + c) = v;
     }
