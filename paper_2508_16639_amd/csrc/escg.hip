@@ -67,32 +67,42 @@ __device__ __forceinline__ bool stop_met(const uint32_t *c, uint32_t S,
 }
 
 // Counts sites of value 0..S among ndw dwords of LDS; adds into cnt[0..S]
-// (LDS, zeroed beforehand).  Bytes that are not sites hold kPadByte, which
-// matches no species.
+// (LDS, zeroed beforehand).  Bytes that are not sites hold pad_byte(S),
+// which matches no species.  SM == 8: one-hot byte codes (values 0..7); else
+// byte compares against every species.
 template <int SM>
 __device__ __forceinline__ void count_dwords(const uint32_t *lat32,
                                              uint32_t ndw, uint32_t S,
                                              uint32_t *cnt)
 {
-    uint32_t ne[SM];
+    uint32_t c[SM];
 #pragma unroll
     for (int s = 0; s < SM; ++s)
-        ne[s] = 0;
+        c[s] = 0;
     uint32_t mine = 0;
     for (uint32_t i = threadIdx.x; i < ndw; i += blockDim.x) {
         const uint32_t v = lat32[i];
-        ++mine;
+        if (SM == 8) {
+            const uint32_t h = one_hot_bytes(v);
 #pragma unroll
-        for (int s = 0; s < SM; ++s)
-            if ((uint32_t)s <= S)
-                ne[s] += bytes_ne(v, (uint32_t)s);
+            for (int s = 0; s < SM; ++s)
+                if ((uint32_t)s <= S)
+                    c[s] += __popc(h & (0x01010101u << s));
+        } else {
+            ++mine;
+#pragma unroll
+            for (int s = 0; s < SM; ++s)
+                if ((uint32_t)s <= S)
+                    c[s] += bytes_ne(v, (uint32_t)s);
+        }
     }
 #pragma unroll
     for (int s = 0; s < SM; ++s) {
         if ((uint32_t)s <= S) {
-            const uint32_t c = wave_sum(4u * mine - ne[s]);
-            if ((threadIdx.x & 63u) == 0 && c)
-                atomicAdd(&cnt[s], c);
+            const uint32_t tot =
+                wave_sum(SM == 8 ? c[s] : 4u * mine - c[s]);
+            if ((threadIdx.x & 63u) == 0 && tot)
+                atomicAdd(&cnt[s], tot);
         }
     }
 }
@@ -117,7 +127,7 @@ __device__ void run_job_lds(const JobDev &J, uint8_t *base, uint8_t *smem)
     if (LS != L)
         for (uint32_t r = tid; r < L; r += nt)
             for (uint32_t c = L; c < LS; ++c)
-                lat[r * LS + c] = kPadByte;
+                lat[r * LS + c] = pad_byte(S);
     if (J.init) {
         const uint32_t nw = (L * L) >> 2;
         for (uint32_t i = tid; i < nw; i += nt) {
@@ -602,26 +612,34 @@ __global__ __launch_bounds__(256) void densities_kernel(const uint32_t *lat32,
     if (threadIdx.x < 32)
         s_cnt[threadIdx.x] = 0;
     __syncthreads();
-    uint32_t ne[SM];
+    uint32_t c[SM];
 #pragma unroll
     for (int s = 0; s < SM; ++s)
-        ne[s] = 0;
+        c[s] = 0;
     uint32_t mine = 0;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ndw;
          i += gridDim.x * blockDim.x) {
         const uint32_t v = lat32[i];
-        ++mine;
+        if (SM == 8) {
+            const uint32_t h = one_hot_bytes(v);
 #pragma unroll
-        for (int s = 0; s < SM; ++s)
-            if ((uint32_t)s <= S)
-                ne[s] += bytes_ne(v, (uint32_t)s);
+            for (int s = 0; s < SM; ++s)
+                if ((uint32_t)s <= S)
+                    c[s] += __popc(h & (0x01010101u << s));
+        } else {
+            ++mine;
+#pragma unroll
+            for (int s = 0; s < SM; ++s)
+                if ((uint32_t)s <= S)
+                    c[s] += bytes_ne(v, (uint32_t)s);
+        }
     }
 #pragma unroll
     for (int s = 0; s < SM; ++s) {
         if ((uint32_t)s <= S) {
-            const uint32_t c = wave_sum(4u * mine - ne[s]);
-            if ((threadIdx.x & 63u) == 0 && c)
-                atomicAdd(&s_cnt[s], c);
+            const uint32_t tot = wave_sum(SM == 8 ? c[s] : 4u * mine - c[s]);
+            if ((threadIdx.x & 63u) == 0 && tot)
+                atomicAdd(&s_cnt[s], tot);
         }
     }
     __syncthreads();

@@ -185,12 +185,31 @@ __device__ __forceinline__ uint32_t bytes_ne(uint32_t v, uint32_t s)
     return __popc(((v ^ (s * 0x01010101u)) + 0x7F7F7F7Fu) & 0x80808080u);
 }
 
+// Sum over the 64 lanes of a wave, returned to every lane.  DPP adds within
+// rows of 16 lanes (row_shr 1, 2, 4, 8 leave each row's sum in its lane 15),
+// then row_bcast:15 and row_bcast:31 carry the row sums to lane 63: all VALU,
+// no LDS round trips.
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v += __shfl_xor(v, o, 64);
-    return v;
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Species counting for values 0..7: v_perm with the byte table
+// {1, 2, 4, ..., 128} maps every byte of a dword to its one-hot code (bytes
+// 12, used as padding, map to 0), so the count of species s in the dword is
+// popcount(code & (0x01010101 << s)).
+constexpr uint32_t kOneHotLo = 0x08040201u; // table bytes 0..3
+constexpr uint32_t kOneHotHi = 0x80402010u; // table bytes 4..7
+
+__device__ __forceinline__ uint32_t one_hot_bytes(uint32_t v)
+{
+    return __builtin_amdgcn_perm(kOneHotHi, kOneHotLo, v);
 }
 
 } // namespace escg

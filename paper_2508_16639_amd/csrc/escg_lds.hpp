@@ -2,7 +2,7 @@
 //
 // Layout (byte offsets from the kernel's dynamic LDS base): dominance masks,
 // two count rows, the quad selector table, the rule tables, then the lattice
-// with row stride LS = L rounded up to 8 (padding bytes hold kPadByte).
+// with row stride LS = L rounded up to 8 (padding bytes hold pad_byte(S)).
 #pragma once
 
 #include "escg_quad.hpp"
@@ -14,7 +14,12 @@ constexpr uint32_t kOffDom = 0;      // 32 u32 dominance masks
 constexpr uint32_t kOffCnt = 128;    // 2 x 32 u32 count rows
 constexpr uint32_t kOffSel = 512;    // 256 uint2 selectors
 constexpr uint32_t kOffRule = 2560;  // 3 * Sp * Sp u16 rule tables
-constexpr uint8_t kPadByte = 0x40;   // row padding: matches no species
+// Row padding must match no species: for S <= 7 (one-hot counting) it is
+// 12, which v_perm maps to a zero byte; above that 0x40, past every species.
+__host__ __device__ inline uint8_t pad_byte(uint32_t S)
+{
+    return S <= 7 ? (uint8_t)12 : (uint8_t)0x40;
+}
 
 __host__ __device__ inline uint32_t species_pow2(uint32_t S)
 {

@@ -196,28 +196,37 @@ __device__ inline void tile_gather(uint8_t *lat, const uint32_t *nb,
     }
 }
 
-// Adds the interior's species counts into cnt[0..S] (LDS, zeroed).
+// Adds the interior's species counts into cnt[0..S] (LDS, zeroed).  SM == 8:
+// one-hot byte codes (values 0..7); else byte compares per species.
 template <int SM>
 __device__ __forceinline__ void tile_count(const uint8_t *lat,
                                            const TileGeom &G, uint32_t S,
                                            uint32_t *cnt)
 {
     const uint32_t LS = G.LS(), dwr = G.TW >> 2, n = G.TH * dwr;
-    uint32_t ne[SM];
+    uint32_t c[SM];
 #pragma unroll
     for (int s = 0; s < SM; ++s)
-        ne[s] = 0;
+        c[s] = 0;
     uint32_t mine = 0;
     uint32_t r = threadIdx.x / dwr, j = threadIdx.x - r * dwr;
     const uint32_t dr = blockDim.x / dwr, dj = blockDim.x - dr * dwr;
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
         const uint32_t v = *reinterpret_cast<const uint32_t *>(
             lat + (4 + r) * LS + 8 + 4 * j);
-        ++mine;
+        if (SM == 8) {
+            const uint32_t h = one_hot_bytes(v);
 #pragma unroll
-        for (int s = 0; s < SM; ++s)
-            if ((uint32_t)s <= S)
-                ne[s] += bytes_ne(v, (uint32_t)s);
+            for (int s = 0; s < SM; ++s)
+                if ((uint32_t)s <= S)
+                    c[s] += __popc(h & (0x01010101u << s));
+        } else {
+            ++mine;
+#pragma unroll
+            for (int s = 0; s < SM; ++s)
+                if ((uint32_t)s <= S)
+                    c[s] += bytes_ne(v, (uint32_t)s);
+        }
         j += dj;
         r += dr;
         if (j >= dwr) {
@@ -228,9 +237,9 @@ __device__ __forceinline__ void tile_count(const uint8_t *lat,
 #pragma unroll
     for (int s = 0; s < SM; ++s) {
         if ((uint32_t)s <= S) {
-            const uint32_t c = wave_sum(4u * mine - ne[s]);
-            if ((threadIdx.x & 63u) == 0 && c)
-                atomicAdd(&cnt[s], c);
+            const uint32_t tot = wave_sum(SM == 8 ? c[s] : 4u * mine - c[s]);
+            if ((threadIdx.x & 63u) == 0 && tot)
+                atomicAdd(&cnt[s], tot);
         }
     }
 }

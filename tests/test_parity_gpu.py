@@ -90,6 +90,8 @@ CASES = [
     (100, 5, [1, 3], (13.0, 1.0, 1.0), 6),
     (130, 3, [1], (1.0, 1.0, 1.0), 5),
     (192, 31, [1, 4, 9, 16], (0.7, 1.0, 1.3), 3),
+    (100, 7, [1, 2, 4], (1.0, 1.0, 1.0), 5),      # row padding, one-hot counts
+    (130, 13, [1, 2, 5], (1.0, 1.0, 1.0), 4),     # row padding, S >= 12
     (200, 3, [1], (2.0, 1.0, 1.0), 3),
     (256, 5, [1, 3], (51.2, 1.0, 1.0), 3),
     (258, 3, [1], (1.0, 1.0, 1.0), 3),
