@@ -228,7 +228,11 @@ def main():
     escg.lib()
     w = workloads.RPSLS3200
 
-    log(f"[bench] headline {w.name}: warmup {args.warmup}, steps {args.steps}")
+    from paper_2508_16639_amd import autotune
+    shape = autotune.apply_cached(torch, escg, w.L, w.S)
+    plan = escg.tile_plan(w.L, w.S, True)
+    log(f"[bench] headline {w.name}: warmup {args.warmup}, steps {args.steps}, "
+        f"tile plan {plan} (autotuned: {shape is not None})")
     h = headline(args, torch, escg, w)
     log(f"[bench] headline {h['value']:.4e} site-updates/s, "
         f"{h['ms_per_step']:.2f} ms/step, kernel {h['kernel_ms']:.2f} ms")
@@ -257,7 +261,9 @@ def main():
         "config": {"workload": "rpsls_L3200_M1e-5_1000mcs", "L": w.L,
                    "S": w.S, "K": list(w.K), "eps": w.ex, "mcs": w.mcs,
                    "seed": w.seed, "counts_every_mcs": True,
-                   "parallelism": "single GPU, persistent tiled kernel"},
+                   "parallelism": "single GPU, persistent tiled kernel",
+                   "tile_TH_TW_threads": list(plan) if plan else None,
+                   "tile_shape_autotuned": shape is not None},
         "roofline": {"bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -198,6 +198,19 @@ escg_status escg_set_persistent_min_L(uint32_t L_min);
 #define ESCG_ROUTE_PERSISTENT 3u
 uint32_t escg_last_route(void);
 
+/* Tile shape used by the tiled paths for lattice side L (the autotuner's
+ * knob): tiles of TH x TW sites, which must divide L with TW % 8 == 0 and TH
+ * even >= 4 (and L % 8 == 0); TH = TW = 0 removes the override.  A shape
+ * that does not fit the device falls back to the planner's choice.
+ * Process-wide.  EINVAL for an invalid shape. */
+escg_status escg_set_tile_shape(uint32_t L, uint32_t TH, uint32_t TW);
+
+/* The tile shape and workgroup size the persistent (persistent != 0) or
+ * per-MCS tiled path would use for (L, S) on the current device.
+ * EUNSUPPORTED if that path cannot run this L. */
+escg_status escg_tile_plan(uint32_t L, uint32_t S, uint32_t persistent,
+                           uint32_t *TH, uint32_t *TW, uint32_t *threads);
+
 /* Synchronises the current device and reports errors that asynchronous
  * kernels can only record on the device: ESCG_ETIMEOUT if a persistent
  * kernel abandoned a bounded wait for a neighbouring workgroup since the

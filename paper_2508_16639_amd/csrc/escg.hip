@@ -931,6 +931,28 @@ uint32_t tiled_threads(const TileGeom &G)
 
 std::atomic<uint32_t> g_tiled_min_L{400};
 
+// Tile-shape overrides per lattice side (autotuner results), both tiled
+// paths.  Guarded by g_shape_mu.
+std::mutex g_shape_mu;
+std::map<uint32_t, std::pair<uint32_t, uint32_t>> g_shape_override;
+
+bool shape_override(uint32_t L, uint32_t &TH, uint32_t &TW)
+{
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    auto it = g_shape_override.find(L);
+    if (it == g_shape_override.end())
+        return false;
+    TH = it->second.first;
+    TW = it->second.second;
+    return true;
+}
+
+bool valid_shape(uint32_t L, uint32_t TH, uint32_t TW)
+{
+    return L % 8 == 0 && TW >= 8 && TW % 8 == 0 && L % TW == 0 && TH >= 4 &&
+           TH % 2 == 0 && L % TH == 0;
+}
+
 TiledPlan plan_tiled_uncached(uint32_t L, uint32_t S)
 {
     TiledPlan best;
@@ -940,11 +962,13 @@ TiledPlan plan_tiled_uncached(uint32_t L, uint32_t S)
     const int cus = std::max(1, di.cus);
     const size_t lds_max = di.lds_max ? di.lds_max : 65536;
     double best_cost = 1e300;
+    uint32_t oTH = 0, oTW = 0;
+    const bool forced = shape_override(L, oTH, oTW) && valid_shape(L, oTH, oTW);
     for (uint32_t TW = 8; TW <= L; TW += 8) {
-        if (L % TW)
+        if (L % TW || (forced && TW != oTW))
             continue;
         for (uint32_t TH = 4; TH <= L; TH += 2) {
-            if (L % TH)
+            if (L % TH || (forced && TH != oTH))
                 continue;
             TileGeom G{L, TH, TW, L / TH, L / TW};
             const uint32_t T = G.TY * G.TX;
@@ -979,10 +1003,14 @@ TiledPlan plan_tiled_uncached(uint32_t L, uint32_t S)
 TiledPlan plan_tiled(uint32_t L, uint32_t S)
 {
     static std::mutex mu;
-    static std::map<std::tuple<int, uint32_t, bool>, TiledPlan> cache;
+    static std::map<std::tuple<int, uint32_t, bool, uint32_t, uint32_t>,
+                    TiledPlan>
+        cache;
     int dev = 0;
     (void)hipGetDevice(&dev);
-    const auto key = std::make_tuple(dev, L, S <= 7);
+    uint32_t oTH = 0, oTW = 0;
+    shape_override(L, oTH, oTW);
+    const auto key = std::make_tuple(dev, L, S <= 7, oTH, oTW);
     {
         std::lock_guard<std::mutex> lk(mu);
         auto it = cache.find(key);
@@ -1008,11 +1036,13 @@ TiledPlan plan_step_uncached(uint32_t L, uint32_t S)
     const double cus = std::max(1, di.cus);
     const size_t lds_max = di.lds_max ? di.lds_max : 65536;
     double best_cost = 1e300;
+    uint32_t oTH = 0, oTW = 0;
+    const bool forced = shape_override(L, oTH, oTW) && valid_shape(L, oTH, oTW);
     for (uint32_t TW = 8; TW <= L && TW <= 512; TW += 8) {
-        if (L % TW)
+        if (L % TW || (forced && TW != oTW))
             continue;
         for (uint32_t TH = 4; TH <= L && TH <= 512; TH += 2) {
-            if (L % TH)
+            if (L % TH || (forced && TH != oTH))
                 continue;
             TileGeom G{L, TH, TW, L / TH, L / TW};
             const size_t lds = (size_t)lattice_lds_offset(S) +
@@ -1040,10 +1070,14 @@ TiledPlan plan_step_uncached(uint32_t L, uint32_t S)
 TiledPlan plan_step(uint32_t L, uint32_t S)
 {
     static std::mutex mu;
-    static std::map<std::tuple<int, uint32_t, bool>, TiledPlan> cache;
+    static std::map<std::tuple<int, uint32_t, bool, uint32_t, uint32_t>,
+                    TiledPlan>
+        cache;
     int dev = 0;
     (void)hipGetDevice(&dev);
-    const auto key = std::make_tuple(dev, L, S <= 7);
+    uint32_t oTH = 0, oTW = 0;
+    shape_override(L, oTH, oTW);
+    const auto key = std::make_tuple(dev, L, S <= 7, oTH, oTW);
     {
         std::lock_guard<std::mutex> lk(mu);
         auto it = cache.find(key);
@@ -1382,6 +1416,34 @@ escg_status escg_set_single_lds_max_L(uint32_t L)
 }
 
 uint32_t escg_last_route(void) { return g_last_route; }
+
+escg_status escg_set_tile_shape(uint32_t L, uint32_t TH, uint32_t TW)
+{
+    if (TH == 0 && TW == 0) {
+        std::lock_guard<std::mutex> lk(g_shape_mu);
+        g_shape_override.erase(L);
+        return ESCG_OK;
+    }
+    if (!valid_shape(L, TH, TW))
+        return ESCG_EINVAL;
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    g_shape_override[L] = {TH, TW};
+    return ESCG_OK;
+}
+
+escg_status escg_tile_plan(uint32_t L, uint32_t S, uint32_t persistent,
+                           uint32_t *TH, uint32_t *TW, uint32_t *threads)
+{
+    if (!TH || !TW || !threads || S < 1 || S > ESCG_MAX_SPECIES)
+        return ESCG_EINVAL;
+    const TiledPlan p = persistent ? plan_tiled(L, S) : plan_step(L, S);
+    if (!p.ok)
+        return ESCG_EUNSUPPORTED;
+    *TH = p.G.TH;
+    *TW = p.G.TW;
+    *threads = p.threads;
+    return ESCG_OK;
+}
 
 escg_status escg_set_persistent_min_L(uint32_t L)
 {

@@ -47,7 +47,8 @@ EXPORTS = ("escg_status_str", "escg_last_error", "escg_circulant_dom", "escg_dom
            "escg_thresholds", "escg_init", "escg_densities", "escg_step_mcs",
            "escg_run_until_extinction", "escg_batch_max_L", "escg_batch_run",
            "escg_set_single_lds_max_L", "escg_set_persistent_min_L",
-           "escg_async_status", "escg_last_route")
+           "escg_async_status", "escg_last_route", "escg_set_tile_shape",
+           "escg_tile_plan")
 
 _lib = None
 
@@ -88,6 +89,8 @@ def lib():
     L.escg_set_single_lds_max_L.argtypes = [u32]
     L.escg_set_persistent_min_L.argtypes = [u32]
     L.escg_async_status.argtypes = [C.c_int]
+    L.escg_set_tile_shape.argtypes = [u32, u32, u32]
+    L.escg_tile_plan.argtypes = [u32, u32, u32, u32p, u32p, u32p]
     L.escg_last_route.argtypes = []
     L.escg_last_route.restype = u32
     for name in EXPORTS:
@@ -171,6 +174,23 @@ def batch_max_L(S: int = 3) -> int:
 def set_persistent_min_L(L: int) -> None:
     _check(lib().escg_set_persistent_min_L(int(L)),
            "escg_set_persistent_min_L")
+
+
+def set_tile_shape(L: int, TH: int = 0, TW: int = 0) -> None:
+    """Force the tiled paths' tile shape for side L (0, 0 clears)."""
+    _check(lib().escg_set_tile_shape(int(L), int(TH), int(TW)),
+           "escg_set_tile_shape")
+
+
+def tile_plan(L: int, S: int, persistent: bool = True):
+    """(TH, TW, threads) the tiled path would use, or None."""
+    a, b, c = C.c_uint32(), C.c_uint32(), C.c_uint32()
+    s = lib().escg_tile_plan(int(L), int(S), 1 if persistent else 0,
+                             C.byref(a), C.byref(b), C.byref(c))
+    if s == EUNSUPPORTED:
+        return None
+    _check(s, "escg_tile_plan")
+    return a.value, b.value, c.value
 
 
 def last_route() -> str:
