@@ -232,7 +232,8 @@ def main():
     shape = autotune.apply_cached(torch, escg, w.L, w.S)
     plan = escg.tile_plan(w.L, w.S, True)
     log(f"[bench] headline {w.name}: warmup {args.warmup}, steps {args.steps}, "
-        f"tile plan {plan} (autotuned: {shape is not None})")
+        f"tile plan {plan} (autotuned: {shape is not None}, "
+        f"device {autotune.device_key(torch)})")
     h = headline(args, torch, escg, w)
     log(f"[bench] headline {h['value']:.4e} site-updates/s, "
         f"{h['ms_per_step']:.2f} ms/step, kernel {h['kernel_ms']:.2f} ms")

@@ -37,8 +37,16 @@ def candidates(L: int, cus: int, max_tiles_per_cu: int = 3
     return out
 
 
+def device_key(torch) -> str:
+    """Architecture and compute-unit count: what the tile shape depends on
+    (marketing names differ between driver versions)."""
+    prop = torch.cuda.get_device_properties(0)
+    arch = getattr(prop, "gcnArchName", "") or torch.cuda.get_device_name(0)
+    return f"{arch.split(':')[0]}|cus={prop.multi_processor_count}"
+
+
 def _key(torch, L: int, S: int) -> str:
-    return f"{torch.cuda.get_device_name(0)}|L={L}|S<=7={int(S <= 7)}"
+    return f"{device_key(torch)}|L={L}|S<=7={int(S <= 7)}"
 
 
 def load_cache() -> Dict[str, dict]:

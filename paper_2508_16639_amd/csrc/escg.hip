@@ -108,21 +108,18 @@ __device__ __forceinline__ void count_dwords(const uint32_t *lat32,
 }
 
 template <bool kPacked>
-__device__ void run_job_lds(const JobDev &J, uint8_t *base, uint8_t *smem)
+__device__ void run_job_lds(const JobDev &J, uint8_t *base, uint8_t *smem,
+                            LdsTables<kPacked ? 8 : 32> &TB)
 {
-    uint32_t *s_dom = reinterpret_cast<uint32_t *>(smem + kOffDom);
-    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(smem + kOffCnt);
+    uint32_t *s_cnt = TB.cnt;
     const uint32_t tid = threadIdx.x, nt = blockDim.x;
     const uint32_t L = J.L, S = J.S, LS = row_stride(L);
-    uint8_t *lat = smem + lattice_lds_offset(S);
+    uint8_t *lat = smem;
     uint32_t *lat32 = reinterpret_cast<uint32_t *>(lat);
     const uint32_t k0 = (uint32_t)J.seed, k1 = (uint32_t)(J.seed >> 32);
     uint8_t *g = base + J.lat_off;
 
-    if (tid < 32)
-        s_dom[tid] = J.dom[tid];
-    if (tid < 64)
-        s_cnt[tid] = 0;
+    setup_tables(TB, J.dom);
     // row padding bytes match no species
     if (LS != L)
         for (uint32_t r = tid; r < L; r += nt)
@@ -155,10 +152,7 @@ __device__ void run_job_lds(const JobDev &J, uint8_t *base, uint8_t *smem)
         }
     }
     __syncthreads();
-    build_quad_luts(reinterpret_cast<uint2 *>(smem + kOffSel),
-                    reinterpret_cast<uint16_t *>(smem + kOffRule),
-                    species_pow2(S), s_dom);
-    const QuadCtx qc = make_quad_ctx(smem, S, J.T1, J.T2);
+    const QuadCtx qc = make_quad_ctx(TB, J.T1, J.T2);
     const uint32_t Lb = L >> 1, Q = (Lb + 3) >> 2;
     const uint32_t by0 = tid / Q, qx0 = tid - by0 * Q;
     const uint32_t dby = nt / Q, dqx = nt - dby * Q;
@@ -226,7 +220,8 @@ __global__ __launch_bounds__(512) void lds_single_kernel(JobDev J,
                                                          uint8_t *base)
 {
     extern __shared__ __align__(16) uint8_t smem[];
-    run_job_lds<kPacked>(J, base, smem);
+    __shared__ LdsTables<kPacked ? 8 : 32> TB;
+    run_job_lds<kPacked>(J, base, smem, TB);
 }
 
 template <bool kPacked>
@@ -235,16 +230,16 @@ __global__ __launch_bounds__(512) void lds_batch_kernel(
     uint32_t n, uint32_t *queue, uint8_t *base)
 {
     extern __shared__ __align__(16) uint8_t smem[];
-    __shared__ uint32_t s_next;
+    __shared__ LdsTables<kPacked ? 8 : 32> TB;
     for (;;) {
         if (threadIdx.x == 0)
-            s_next = atomicAdd(queue, 1u);
+            TB.misc[0] = atomicAdd(queue, 1u);
         __syncthreads();
-        const uint32_t qi = s_next;
+        const uint32_t qi = TB.misc[0];
         __syncthreads();
         if (qi >= n)
             return;
-        run_job_lds<kPacked>(jobs[order[qi]], base, smem);
+        run_job_lds<kPacked>(jobs[order[qi]], base, smem, TB);
     }
 }
 
@@ -445,10 +440,10 @@ template <bool kPacked>
 __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
 {
     extern __shared__ __align__(16) uint8_t smem[];
-    uint32_t *s_dom = reinterpret_cast<uint32_t *>(smem + kOffDom);
-    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(smem + kOffCnt);
-    uint32_t *s_misc = s_cnt + 64;
-    uint8_t *lat = smem + lattice_lds_offset(a.S);
+    __shared__ LdsTables<kPacked ? 8 : 32> TB;
+    uint32_t *s_cnt = TB.cnt;
+    uint32_t *s_misc = TB.misc;
+    uint8_t *lat = smem;
     const TileGeom G = a.G;
     const uint32_t tid = threadIdx.x, S = a.S;
     const uint32_t T = G.TY * G.TX;
@@ -460,17 +455,9 @@ __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     const uint32_t sd = G.slot_dwords();
 
-    if (tid < 32)
-        s_dom[tid] = a.dom[tid];
-    if (tid < 64)
-        s_cnt[tid] = 0;
     tile_load(lat, a.lattice, G, ty, tx);
-    __syncthreads();
-    build_quad_luts(reinterpret_cast<uint2 *>(smem + kOffSel),
-                    reinterpret_cast<uint16_t *>(smem + kOffRule),
-                    species_pow2(S), s_dom);
-    __syncthreads();
-    const QuadCtx qc = make_quad_ctx(smem, S, a.T1, a.T2);
+    setup_tables(TB, a.dom);
+    const QuadCtx qc = make_quad_ctx(TB, a.T1, a.T2);
 
     bool aborted = false;
     for (uint32_t t = 0; t < a.n_mcs; ++t) {
@@ -543,6 +530,7 @@ struct StepArgs {
     const uint8_t *src;
     uint8_t *dst;
     uint32_t *counts; // this MCS's row (S+1, zeroed) or null
+    const uint32_t *done; // non-null and nonzero: only carry src to dst
     uint64_t seed;
     TileGeom G;
     uint32_t S, T1, T2, replica, t;
@@ -553,23 +541,25 @@ template <bool kPacked>
 __global__ __launch_bounds__(512) void tiled_step_kernel(StepArgs a)
 {
     extern __shared__ __align__(16) uint8_t smem[];
-    uint32_t *s_dom = reinterpret_cast<uint32_t *>(smem + kOffDom);
-    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(smem + kOffCnt);
-    uint8_t *lat = smem + lattice_lds_offset(a.S);
+    __shared__ LdsTables<kPacked ? 8 : 32> TB;
+    uint32_t *s_cnt = TB.cnt;
+    uint8_t *lat = smem;
     const TileGeom G = a.G;
     const uint32_t tid = threadIdx.x, S = a.S;
     const uint32_t ty = blockIdx.x / G.TX, tx = blockIdx.x - ty * G.TX;
-    if (tid < 32) {
-        s_dom[tid] = a.dom[tid];
-        s_cnt[tid] = 0;
+    if (a.done && *a.done) { // stopped: carry the tile over unchanged
+        const uint32_t dwr = G.TW >> 2, R0 = ty * G.TH, g0 = tx * G.TW;
+        for (uint32_t i = tid; i < G.TH * dwr; i += blockDim.x) {
+            const uint32_t r = i / dwr, j = i - r * dwr;
+            const size_t gi = (size_t)(R0 + r) * G.L + g0 + 4 * j;
+            *reinterpret_cast<uint32_t *>(a.dst + gi) =
+                *reinterpret_cast<const uint32_t *>(a.src + gi);
+        }
+        return;
     }
     tile_load(lat, a.src, G, ty, tx);
-    __syncthreads();
-    build_quad_luts(reinterpret_cast<uint2 *>(smem + kOffSel),
-                    reinterpret_cast<uint16_t *>(smem + kOffRule),
-                    species_pow2(S), s_dom);
-    __syncthreads();
-    const QuadCtx qc = make_quad_ctx(smem, S, a.T1, a.T2);
+    setup_tables(TB, a.dom);
+    const QuadCtx qc = make_quad_ctx(TB, a.T1, a.T2);
     tile_mcs(lat, G, ty, tx, a.t, a.replica, (uint32_t)a.seed,
              (uint32_t)(a.seed >> 32), qc);
     tile_store(lat, a.dst, G, ty, tx);
@@ -763,9 +753,15 @@ DeviceInfo device_info()
     return cache[dev];
 }
 
-size_t lds_job_bytes(uint32_t L, uint32_t S)
+// Static LDS of the kernels (tables) and dynamic LDS of a whole lattice.
+size_t static_lds_bytes(uint32_t S)
 {
-    return (size_t)lattice_lds_offset(S) + (size_t)row_stride(L) * L;
+    return S <= 7 ? sizeof(LdsTables<8>) : sizeof(LdsTables<32>);
+}
+
+size_t lds_job_bytes(uint32_t L, uint32_t /*S*/)
+{
+    return (size_t)row_stride(L) * L;
 }
 
 // Largest even L whose whole lattice (plus tables) fits one workgroup's LDS.
@@ -773,7 +769,7 @@ uint32_t lds_max_L(uint32_t S)
 {
     const DeviceInfo di = device_info();
     const size_t lds = di.lds_max ? di.lds_max : 65536;
-    const size_t reserve = 64; // static LDS of the kernels
+    const size_t reserve = static_lds_bytes(S) + 64;
     uint32_t L = 2;
     while (lds_job_bytes(L + 2, S) + reserve <= lds)
         L += 2;
@@ -972,9 +968,8 @@ TiledPlan plan_tiled_uncached(uint32_t L, uint32_t S)
                 continue;
             TileGeom G{L, TH, TW, L / TH, L / TW};
             const uint32_t T = G.TY * G.TX;
-            const size_t lds = (size_t)lattice_lds_offset(S) +
-                               G.region_bytes() + 64;
-            if (lds > lds_max)
+            const size_t lds = G.region_bytes();
+            if (lds + static_lds_bytes(S) + 64 > lds_max)
                 continue;
             const uint32_t nt = tiled_threads(G);
             const void *fn = S <= 7 ? (const void *)tiled_persistent_kernel<true>
@@ -1045,9 +1040,8 @@ TiledPlan plan_step_uncached(uint32_t L, uint32_t S)
             if (L % TH || (forced && TH != oTH))
                 continue;
             TileGeom G{L, TH, TW, L / TH, L / TW};
-            const size_t lds = (size_t)lattice_lds_offset(S) +
-                               G.region_bytes() + 64;
-            if (lds > lds_max)
+            const size_t lds = G.region_bytes();
+            if (lds + static_lds_bytes(S) + 64 > lds_max)
                 continue;
             const double T = (double)G.TY * G.TX;
             const double area = (double)(TH + 8) * (TW + 16);
@@ -1088,6 +1082,37 @@ TiledPlan plan_step(uint32_t L, uint32_t S)
     std::lock_guard<std::mutex> lk(mu);
     cache[key] = plan;
     return plan;
+}
+
+StepArgs step_args(const escg_params *p, const Derived &d,
+                   const TiledPlan &sp)
+{
+    StepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.seed = p->seed;
+    a.G = sp.G;
+    a.S = p->S;
+    a.T1 = d.T1;
+    a.T2 = d.T2;
+    a.replica = p->replica;
+    for (int i = 0; i < 32; ++i)
+        a.dom[i] = p->dom[i];
+    return a;
+}
+
+void launch_step(const StepArgs &a, const TiledPlan &sp, bool small,
+                 hipStream_t st)
+{
+    const uint32_t T = sp.G.TY * sp.G.TX;
+    const void *fn = small ? (const void *)tiled_step_kernel<true>
+                           : (const void *)tiled_step_kernel<false>;
+    allow_dynamic_lds(fn, sp.lds);
+    if (small)
+        hipLaunchKernelGGL(tiled_step_kernel<true>, dim3(T), dim3(sp.threads),
+                           sp.lds, st, a);
+    else
+        hipLaunchKernelGGL(tiled_step_kernel<false>, dim3(T),
+                           dim3(sp.threads), sp.lds, st, a);
 }
 
 // Runs n_mcs MCS of a large lattice with the persistent kernel.  Returns
@@ -1286,32 +1311,14 @@ escg_status escg_step_mcs(const escg_params *p, uint8_t *d_lattice,
     uint8_t *cur = d_lattice, *nxt = other;
     const TiledPlan sp = plan_step(L, S);
     if (sp.ok) {
-        StepArgs a;
-        std::memset(&a, 0, sizeof(a));
-        a.seed = p->seed;
-        a.G = sp.G;
-        a.S = S;
-        a.T1 = d.T1;
-        a.T2 = d.T2;
-        a.replica = p->replica;
-        for (int i = 0; i < 32; ++i)
-            a.dom[i] = p->dom[i];
-        const void *fn = d.small ? (const void *)tiled_step_kernel<true>
-                                 : (const void *)tiled_step_kernel<false>;
-        allow_dynamic_lds(fn, sp.lds);
-        const uint32_t T = sp.G.TY * sp.G.TX;
+        StepArgs a = step_args(p, d, sp);
         for (uint32_t k = 0; k < n_mcs; ++k) {
             a.src = cur;
             a.dst = nxt;
             a.t = mcs0 + k;
             a.counts =
                 d_counts ? d_counts + (size_t)(k + 1) * (S + 1) : nullptr;
-            if (d.small)
-                hipLaunchKernelGGL(tiled_step_kernel<true>, dim3(T),
-                                   dim3(sp.threads), sp.lds, st, a);
-            else
-                hipLaunchKernelGGL(tiled_step_kernel<false>, dim3(T),
-                                   dim3(sp.threads), sp.lds, st, a);
+            launch_step(a, sp, d.small, st);
             std::swap(cur, nxt);
         }
     } else {
@@ -1369,6 +1376,9 @@ escg_status escg_run_until_extinction(const escg_params *p, uint8_t *d_lattice,
                        0u, S, mode, 0u, d_result);
     TileArgs a = tile_args(p, d);
     a.done = stw;
+    const TiledPlan sp = plan_step(L, S);
+    StepArgs sa = sp.ok ? step_args(p, d, sp) : StepArgs{};
+    sa.done = stw;
     uint8_t *cur = d_lattice, *nxt = other;
     uint32_t launched = 0;
     const uint32_t chunk = 32;
@@ -1385,11 +1395,19 @@ escg_status escg_run_until_extinction(const escg_params *p, uint8_t *d_lattice,
         const uint32_t n = std::min(chunk, max_mcs - launched);
         for (uint32_t k = 0; k < n; ++k) {
             const uint32_t t = launched + k;
-            a.src = cur;
-            a.dst = nxt;
-            a.t = mcs0 + t;
-            a.counts = cnt2 + ((t + 1) & 1u) * 32;
-            launch_tile_mcs(a, d.small, st);
+            if (sp.ok) {
+                sa.src = cur;
+                sa.dst = nxt;
+                sa.t = mcs0 + t;
+                sa.counts = cnt2 + ((t + 1) & 1u) * 32;
+                launch_step(sa, sp, d.small, st);
+            } else {
+                a.src = cur;
+                a.dst = nxt;
+                a.t = mcs0 + t;
+                a.counts = cnt2 + ((t + 1) & 1u) * 32;
+                launch_tile_mcs(a, d.small, st);
+            }
             hipLaunchKernelGGL(check_stop_kernel, dim3(1), dim3(64), 0, st,
                                stw, cnt2, (t + 1) & 1u, S, mode, t + 1,
                                d_result);

@@ -1,19 +1,26 @@
 // escg_lds.hpp -- one Monte Carlo step on a lattice held whole in LDS.
 //
-// Layout (byte offsets from the kernel's dynamic LDS base): dominance masks,
-// two count rows, the quad selector table, the rule tables, then the lattice
-// with row stride LS = L rounded up to 8 (padding bytes hold pad_byte(S)).
+// Layout: the tables live in static LDS (LdsTables); the kernel's dynamic
+// LDS holds the lattice with row stride LS = L rounded up to 8 (padding
+// bytes hold pad_byte(S)).
 #pragma once
 
 #include "escg_quad.hpp"
 
 namespace escg {
 
-// LDS layout of the whole-lattice kernels (byte offsets).
-constexpr uint32_t kOffDom = 0;      // 32 u32 dominance masks
-constexpr uint32_t kOffCnt = 128;    // 2 x 32 u32 count rows
-constexpr uint32_t kOffSel = 512;    // 256 uint2 selectors
-constexpr uint32_t kOffRule = 2560;  // 3 * Sp * Sp u16 rule tables
+// Per-workgroup tables in static LDS (their addresses are known at compile
+// time, so table lookups need no base-address arithmetic).  SP = 8 serves
+// S <= 7 (values 0..7), SP = 32 any S <= 31.
+template <int SP>
+struct LdsTables {
+    uint2 sel[256];               // {gather, scatter} selectors
+    uint16_t rule[3 * SP * SP];   // (x', y') per action, x, y
+    uint32_t dom[32];             // dominance masks
+    uint32_t cnt[64];             // two count rows
+    uint32_t misc[4];
+};
+
 // Row padding must match no species: for S <= 7 (one-hot counting) it is
 // 12, which v_perm maps to a zero byte; above that 0x40, past every species.
 __host__ __device__ inline uint8_t pad_byte(uint32_t S)
@@ -21,18 +28,6 @@ __host__ __device__ inline uint8_t pad_byte(uint32_t S)
     return S <= 7 ? (uint8_t)12 : (uint8_t)0x40;
 }
 
-__host__ __device__ inline uint32_t species_pow2(uint32_t S)
-{
-    uint32_t sp = 8;
-    while (sp < S + 1)
-        sp <<= 1;
-    return sp;
-}
-__host__ __device__ inline uint32_t lattice_lds_offset(uint32_t S)
-{
-    const uint32_t sp = species_pow2(S);
-    return (kOffRule + 6 * sp * sp + 15) & ~15u;
-}
 __host__ __device__ inline uint32_t row_stride(uint32_t L)
 {
     return (L + 7) & ~7u;
@@ -91,21 +86,34 @@ __device__ __forceinline__ void lds_mcs(uint8_t *lat, uint32_t L, uint32_t LS,
     }
 }
 
-__device__ inline QuadCtx make_quad_ctx(uint8_t *smem, uint32_t S,
-                                        uint32_t T1, uint32_t T2)
+template <int SP>
+__device__ inline QuadCtx make_quad_ctx(const LdsTables<SP> &T, uint32_t T1,
+                                        uint32_t T2)
 {
     QuadCtx qc;
-    qc.sel = reinterpret_cast<const uint2 *>(smem + kOffSel);
-    qc.rule = smem + kOffRule;
-    const uint32_t sp = species_pow2(S);
+    qc.sel = T.sel;
+    qc.rule = reinterpret_cast<const uint8_t *>(T.rule);
     const ActionSplit a = split_actions(T1, T2);
     qc.W1 = a.W1;
     qc.W2 = a.W2;
-    qc.B1 = a.a1 * sp * sp * 2u;
-    qc.B2 = a.a2 * sp * sp * 2u;
-    qc.B3 = a.a3 * sp * sp * 2u;
-    qc.dotw = (2u * sp) | (2u << 8);
+    qc.B1 = a.a1 * SP * SP * 2u;
+    qc.B2 = a.a2 * SP * SP * 2u;
+    qc.B3 = a.a3 * SP * SP * 2u;
+    qc.dotw = (2u * SP) | (2u << 8);
     return qc;
+}
+
+// Fills the tables of a job (dominance masks from `dom`, global or LDS).
+template <int SP>
+__device__ inline void setup_tables(LdsTables<SP> &T, const uint32_t *dom)
+{
+    for (uint32_t i = threadIdx.x; i < 32; i += blockDim.x)
+        T.dom[i] = dom[i];
+    for (uint32_t i = threadIdx.x; i < 64; i += blockDim.x)
+        T.cnt[i] = 0;
+    __syncthreads();
+    build_quad_luts(T.sel, T.rule, SP, T.dom);
+    __syncthreads();
 }
 
 } // namespace escg

@@ -119,6 +119,41 @@ def test_step_mcs_bit_exact(case, route):
     assert np.array_equal(c, rc)
 
 
+def _imported_matrices():
+    """Dominance matrices that are not circulant: RPSLS with one edge of the
+    five-species cycle removed, a pair of species that beat each other, and
+    seeded random matrices with S = 8 and S = 20 (the rule reads any 0/1
+    matrix; the diagonal is ignored)."""
+    ablated = O.circulant_matrix(5, [1, 3]).copy()
+    ablated[0, 1] = 0
+    mutual = np.array([[0, 1, 0], [1, 0, 0], [1, 0, 0]], np.uint8)
+    rng = np.random.default_rng(11)
+    r8 = (rng.random((8, 8)) < 0.4).astype(np.uint8)
+    r20 = (rng.random((20, 20)) < 0.3).astype(np.uint8)
+    np.fill_diagonal(r8, 0)
+    np.fill_diagonal(r20, 0)
+    return [("ablated_rpsls", ablated), ("mutual", mutual), ("rand8", r8),
+            ("rand20", r20)]
+
+
+@pytest.mark.parametrize("name,D", _imported_matrices(),
+                         ids=[m[0] for m in _imported_matrices()])
+@pytest.mark.parametrize("L", [64, 136, 416])
+@pytest.mark.parametrize("route", ["lds", "tiled", "persistent"])
+def test_imported_dominance_bit_exact(name, D, L, route):
+    S = D.shape[0]
+    if route == "lds" and L > escg.batch_max_L(S):
+        pytest.skip("lattice does not fit LDS")
+    route_to(route)
+    p, j = pair(L, S, None, 0.8, 1.0, 1.1, seed=L + S, replica=2, D=D)
+    g0 = random_lattice(L, S, seed=L + 1, domain=5)
+    out, c = gpu_step(p, g0, 3, 3, route=route)
+    ref = g0.copy()
+    rc = O.o2_run(j, ref, 3, 3)
+    assert np.array_equal(out, ref)
+    assert np.array_equal(c, rc)
+
+
 @pytest.mark.parametrize("route", ["lds", "tiled", "persistent"])
 def test_zero_mcs_writes_only_row0(route):
     route_to(route)
@@ -211,3 +246,33 @@ def test_persistent_equals_per_mcs_tiled_long(L, S, K, ex, n):
     assert np.array_equal(a, b)
     assert np.array_equal(ca, cb)
     assert (ca.sum(1) == L * L).all()
+
+
+@pytest.mark.parametrize("shape", [(100, 400), (200, 200), (160, 320),
+                                   (400, 128)])
+def test_tile_shapes_give_identical_bytes(shape):
+    """Autotuner knob: every tile shape of the persistent kernel gives the
+    same lattice and counts as the per-MCS kernel with its default plan."""
+    L, S = 3200, 5
+    p, _ = pair(L, S, [1, 3], 51.2, seed=21)
+    g0 = random_lattice(L, S, seed=8, domain=5)
+    route_to("tiled")
+    ref, cref = gpu_step(p, g0, 7, 6, route="tiled")
+    route_to("persistent")
+    escg.set_tile_shape(L, *shape)
+    try:
+        plan = escg.tile_plan(L, S, True)
+        got, cgot = gpu_step(p, g0, 7, 6)
+        if plan is not None and plan[:2] == shape:
+            assert escg.last_route() == "persistent"
+    finally:
+        escg.set_tile_shape(L, 0, 0)
+    assert np.array_equal(got, ref)
+    assert np.array_equal(cgot, cref)
+
+
+def test_tile_shape_rejects_invalid():
+    with pytest.raises(escg.EscgError):
+        escg.set_tile_shape(3200, 100, 100)   # TW % 8 != 0
+    with pytest.raises(escg.EscgError):
+        escg.set_tile_shape(3200, 3, 400)     # TH odd
