@@ -80,15 +80,16 @@ __device__ __forceinline__ void count_dwords(const uint32_t *lat32,
     for (int s = 0; s < SM; ++s)
         c[s] = 0;
     uint32_t mine = 0;
-    for (uint32_t i = threadIdx.x; i < ndw; i += blockDim.x) {
-        const uint32_t v = lat32[i];
-        if (SM == 8) {
-            const uint32_t h = one_hot_bytes(v);
-#pragma unroll
-            for (int s = 0; s < SM; ++s)
-                if ((uint32_t)s <= S)
-                    c[s] += __popc(h & (0x01010101u << s));
-        } else {
+    if constexpr (SM == 8) {
+        // ndw is even (rows are padded to a multiple of 8 bytes)
+        const uint2 *lat64 = reinterpret_cast<const uint2 *>(lat32);
+        for (uint32_t i = threadIdx.x; i < (ndw >> 1); i += blockDim.x) {
+            const uint2 v = lat64[i];
+            count_pair8(v.x, v.y, c);
+        }
+    } else {
+        for (uint32_t i = threadIdx.x; i < ndw; i += blockDim.x) {
+            const uint32_t v = lat32[i];
             ++mine;
 #pragma unroll
             for (int s = 0; s < SM; ++s)
@@ -426,8 +427,7 @@ __device__ uint32_t g_async_error;
 
 struct TiledArgs {
     uint8_t *lattice;   // in/out
-    uint32_t *exch;     // 2 * T * slot_dwords exchange area
-    uint32_t *flags;    // T words, zeroed: MCS completed per tile
+    uint32_t *exch;     // 2 * T * slot_dwords exchange area, slots pre-tagged
     uint32_t *abort;    // 1 word, zeroed
     uint32_t *counts;   // rows (n+1)*(S+1) with rows 1..n zeroed, or null
     uint64_t seed;
@@ -455,68 +455,46 @@ __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     const uint32_t sd = G.slot_dwords();
 
+    if (tid == 0)
+        s_misc[0] = 0;
     tile_load(lat, a.lattice, G, ty, tx);
-    setup_tables(TB, a.dom);
+    setup_tables(TB, a.dom); // ends with a barrier
     const QuadCtx qc = make_quad_ctx(TB, a.T1, a.T2);
 
     bool aborted = false;
     for (uint32_t t = 0; t < a.n_mcs; ++t) {
         tile_mcs(lat, G, ty, tx, a.mcs0 + t, a.replica, k0, k1, qc);
-        const uint32_t slot = (t + 1) & 1u;
-        tile_publish(lat, a.exch + (size_t)(2 * tile + slot) * sd, G);
-        // every wave's strip stores (sc1, device-coherent) must have
-        // completed before the flag announces them; no cache maintenance
-        // is needed because neither side caches the exchange area
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        if (tid == 0)
-            __hip_atomic_store(&a.flags[tile], t + 1, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        if (a.counts) {
-            if (kPacked)
-                tile_count<8>(lat, G, S, s_cnt);
-            else
-                tile_count<32>(lat, G, S, s_cnt);
-        }
-        // wait for the eight neighbours (bounded)
-        if (tid < 9 && tid != 4) {
-            const uint32_t dy = tid / 3, dx = tid - dy * 3;
-            const uint32_t ny = (ty + G.TY + dy - 1) % G.TY;
-            const uint32_t nx = (tx + G.TX + dx - 1) % G.TX;
-            const uint32_t *f = &a.flags[ny * G.TX + nx];
-            // relaxed sc1 polls; the barrier below orders the strip loads
-            uint32_t spins = 0;
-            while (__hip_atomic_load(f, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT) < t + 1) {
-                if ((++spins & 63u) == 0) {
-                    if (__hip_atomic_load(a.abort, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT))
-                        break;
-                    if (spins > a.spin_limit) {
-                        __hip_atomic_store(a.abort, 1u, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                        atomicOr(&g_async_error, 1u);
-                        break;
-                    }
+        // publish, count and gather touch disjoint parts of the region:
+        // border strips and interior are read, only the halo is written
+        const uint32_t e = t + 1, slot = exch_slot(e), tag = exch_tag(e);
+        tile_publish(lat, a.exch + (size_t)(slot * T + tile) * sd, G, tag);
+        // the tags replace flags: each halo word is awaited on its own; the
+        // counts run while the first halo loads are in flight
+        const uint32_t st = tile_gather(
+            lat, a.exch, G, ty, tx, slot, tag, a.abort, a.spin_limit, [&] {
+                if (a.counts) {
+                    if (kPacked)
+                        tile_count<8>(lat, G, S, s_cnt);
+                    else
+                        tile_count<32>(lat, G, S, s_cnt);
                 }
-                __builtin_amdgcn_s_sleep(1);
+            });
+        if (st) {
+            if (st == 2) {
+                xstore(a.abort, 1u);
+                atomicOr(&g_async_error, 1u);
             }
+            s_misc[0] = 1;
         }
         __syncthreads();
         if (a.counts && tid <= S) {
             atomicAdd(&a.counts[(size_t)(t + 1) * (S + 1) + tid], s_cnt[tid]);
             s_cnt[tid] = 0;
         }
-        if (tid == 0)
-            s_misc[0] = __hip_atomic_load(a.abort, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
         if (s_misc[0]) {
             aborted = true;
             break;
         }
-        tile_gather(lat, a.exch, G, ty, tx, slot); // sc1 loads
-        __syncthreads();
     }
     if (!aborted)
         tile_store(lat, a.lattice, G, ty, tx);
@@ -972,6 +950,8 @@ TiledPlan plan_tiled_uncached(uint32_t L, uint32_t S)
             if (lds + static_lds_bytes(S) + 64 > lds_max)
                 continue;
             const uint32_t nt = tiled_threads(G);
+            if (G.TW / 4 > nt) // tile_count walks one column per thread
+                continue;
             const void *fn = S <= 7 ? (const void *)tiled_persistent_kernel<true>
                                     : (const void *)tiled_persistent_kernel<false>;
             allow_dynamic_lds(fn, lds);
@@ -1128,9 +1108,8 @@ escg_status run_tiled_persistent(const escg_params *p, const Derived &d,
         return ESCG_EUNSUPPORTED;
     const TileGeom G = plan.G;
     const uint32_t T = G.TY * G.TX;
-    const size_t exch_bytes = (size_t)2 * T * G.slot_dwords() * 4;
-    const size_t flags_off = (exch_bytes + 255) & ~(size_t)255;
-    const size_t total = flags_off + (size_t)(T + 64) * 4;
+    const size_t slot_area = (size_t)T * G.slot_dwords(); // dwords
+    const size_t total = (2 * slot_area + 64) * 4;
     uint8_t *scr = nullptr;
     if (hipMallocAsync((void **)&scr, total, st) != hipSuccess)
         return ESCG_ENOMEM;
@@ -1138,8 +1117,7 @@ escg_status run_tiled_persistent(const escg_params *p, const Derived &d,
     std::memset(&a, 0, sizeof(a));
     a.lattice = lattice;
     a.exch = reinterpret_cast<uint32_t *>(scr);
-    a.flags = reinterpret_cast<uint32_t *>(scr + flags_off);
-    a.abort = a.flags + T;
+    a.abort = a.exch + 2 * slot_area;
     a.counts = counts;
     a.seed = p->seed;
     a.G = G;
@@ -1149,10 +1127,13 @@ escg_status run_tiled_persistent(const escg_params *p, const Derived &d,
     a.replica = p->replica;
     a.mcs0 = mcs0;
     a.n_mcs = n_mcs;
-    a.spin_limit = 1u << 26; // polls (~seconds), then abort with an error
+    a.spin_limit = 1u << 22; // polls (seconds), then abort with an error
     for (int i = 0; i < 32; ++i)
         a.dom[i] = p->dom[i];
-    launch_fill(a.flags, T + 64, 0, st);
+    // slot 0 tagged 0, slot 1 tagged 1: neither matches its first use
+    launch_fill(a.exch, slot_area, exch_tag(2) ^ 0x80808080u, st);
+    launch_fill(a.exch + slot_area, slot_area, exch_tag(1) ^ 0x80808080u, st);
+    launch_fill(a.abort, 64, 0, st);
     if (counts)
         launch_fill(counts + (p->S + 1), (size_t)n_mcs * (p->S + 1), 0, st);
     void *args[] = {&a};

@@ -10,7 +10,8 @@
 // corrupts at most one more ring of sites per pass and the interior is exact
 // after four passes.  Between MCS every tile publishes the 4-row / 8-column
 // border strips of its interior into a double-buffered exchange area and
-// rebuilds its halo from the eight neighbours' strips.
+// rebuilds its halo from the eight neighbours' strips, which carry a tag bit
+// that tells fresh words from stale ones.
 //
 // Region coordinates: LDS row r <-> global row R0 - 4 + r, LDS column c <->
 // global column g0 - 8 + c (mod L); row stride LS = TW + 24 (the spare bytes
@@ -125,113 +126,224 @@ __device__ __forceinline__ uint32_t xload(const uint32_t *p)
                              __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Writes the interior's border strips into exchange slot `slot`.
+// Exchange area: two slots per tile, slot s of tile T at dword
+// (s * tiles + T) * slot_dwords.  The strips published after the tile's
+// e-th MCS of a launch go to slot e & 1, every byte carrying the tag bit
+// ((e >> 1) & 1) in bit 7 (species values stay below 0x80).  A reader
+// therefore recognises fresh data word by word, with no separate flag, and
+// a slot's previous content (from MCS e - 2) always carries the other tag.
+// Before the first MCS, slot 0 holds tag 0 and slot 1 tag 1, which the
+// first use of each slot (e = 2, tag 1; e = 1, tag 0) does not match.
+__host__ __device__ inline uint32_t exch_slot(uint32_t e) { return e & 1u; }
+__host__ __device__ inline uint32_t exch_tag(uint32_t e)
+{
+    return ((e >> 1) & 1u) ? 0x80808080u : 0u;
+}
+
+// Writes the interior's border strips, tagged with `tag` (0 or 0x80808080),
+// into one exchange slot.
 __device__ inline void tile_publish(const uint8_t *lat, uint32_t *slot,
-                                    const TileGeom &G)
+                                    const TileGeom &G, uint32_t tag)
 {
     const uint32_t LS = G.LS(), TH = G.TH, TW = G.TW, dwr = TW >> 2;
     uint32_t *top = slot, *bot = slot + TW, *left = slot + 2 * TW,
              *right = left + 2 * TH;
     for (uint32_t i = threadIdx.x; i < 4 * dwr; i += blockDim.x) {
         const uint32_t r = i / dwr, j = i - r * dwr;
-        xstore(top + i, *reinterpret_cast<const uint32_t *>(
-                            lat + (4 + r) * LS + 8 + 4 * j));
-        xstore(bot + i, *reinterpret_cast<const uint32_t *>(
-                            lat + (TH + r) * LS + 8 + 4 * j));
+        xstore(top + i, tag | *reinterpret_cast<const uint32_t *>(
+                                  lat + (4 + r) * LS + 8 + 4 * j));
+        xstore(bot + i, tag | *reinterpret_cast<const uint32_t *>(
+                                  lat + (TH + r) * LS + 8 + 4 * j));
     }
     for (uint32_t i = threadIdx.x; i < 2 * TH; i += blockDim.x) {
         const uint32_t r = i >> 1, j = i & 1u;
-        xstore(left + i, *reinterpret_cast<const uint32_t *>(
-                             lat + (4 + r) * LS + 8 + 4 * j));
-        xstore(right + i, *reinterpret_cast<const uint32_t *>(
-                              lat + (4 + r) * LS + TW + 4 * j));
+        xstore(left + i, tag | *reinterpret_cast<const uint32_t *>(
+                                   lat + (4 + r) * LS + 8 + 4 * j));
+        xstore(right + i, tag | *reinterpret_cast<const uint32_t *>(
+                                    lat + (4 + r) * LS + TW + 4 * j));
     }
 }
 
-// Rebuilds the halo from the neighbours' strips in their slot `s` (nb:
-// base of the exchange area; slot of tile T is nb + (2 T + s) * slot_dwords).
-__device__ inline void tile_gather(uint8_t *lat, const uint32_t *nb,
-                                   const TileGeom &G, uint32_t ty,
-                                   uint32_t tx, uint32_t s)
+// Halo word i of the region (i < 8 * (TW/4 + 4) + 4 * TH): its source in the
+// neighbours' slot `s` and its LDS destination.
+struct HaloWord {
+    const uint32_t *src;
+    uint32_t dst;
+};
+
+struct HaloMap {
+    const uint32_t *sU, *sD, *sUL, *sUR, *sDL, *sDR, *sL, *sR;
+    uint32_t LS, TH, TW, dwr, wdw;
+
+    __device__ HaloMap(const uint32_t *nb, const TileGeom &G, uint32_t ty,
+                       uint32_t tx, uint32_t s)
+    {
+        LS = G.LS();
+        TH = G.TH;
+        TW = G.TW;
+        dwr = TW >> 2;
+        wdw = dwr + 4; // dwords per halo row: 2 + dwr + 2
+        const uint32_t sd = G.slot_dwords(), T = G.TY * G.TX;
+        const uint32_t up = (ty + G.TY - 1) % G.TY, dn = (ty + 1) % G.TY;
+        const uint32_t lf = (tx + G.TX - 1) % G.TX, rt = (tx + 1) % G.TX;
+        const uint32_t *base = nb + (size_t)s * T * sd;
+        auto slot = [&](uint32_t y, uint32_t x) {
+            return base + (size_t)(y * G.TX + x) * sd;
+        };
+        sU = slot(up, tx);
+        sD = slot(dn, tx);
+        sUL = slot(up, lf);
+        sUR = slot(up, rt);
+        sDL = slot(dn, lf);
+        sDR = slot(dn, rt);
+        sL = slot(ty, lf);
+        sR = slot(ty, rt);
+    }
+    __device__ uint32_t count() const { return 8 * wdw + 4 * TH; }
+    __device__ HaloWord at(uint32_t i) const
+    {
+        HaloWord w;
+        if (i < 8 * wdw) {
+            // rows 0..3 from the bottom strips of the tiles above, rows
+            // TH+4.. from the top strips of the tiles below
+            const uint32_t h = i / wdw, j = i - h * wdw;
+            const uint32_t r = h & 3u;
+            const bool topside = h < 4;
+            const uint32_t lr = topside ? r : TH + 4 + r;
+            const uint32_t *mid = topside ? sU + TW : sD;
+            const uint32_t *lft = topside ? sUL + TW : sDL;
+            const uint32_t *rgt = topside ? sUR + TW : sDR;
+            if (j < 2)
+                w.src = lft + r * dwr + dwr - 2 + j;
+            else if (j < dwr + 2)
+                w.src = mid + r * dwr + j - 2;
+            else
+                w.src = rgt + r * dwr + j - 2 - dwr;
+            w.dst = lr * LS + 4 * j;
+        } else {
+            // columns 0..7 and TW+8..TW+15 of rows 4..TH+3 from the right
+            // strip of the left neighbour and the left strip of the right one
+            const uint32_t k = i - 8 * wdw;
+            const uint32_t side = k / (2 * TH), q = k - side * 2 * TH;
+            const uint32_t r = q >> 1, j = q & 1u;
+            w.src = side == 0 ? sL + 2 * TW + 2 * TH + q : sR + 2 * TW + q;
+            w.dst = (4 + r) * LS + (side == 0 ? 4 * j : TW + 8 + 4 * j);
+        }
+        return w;
+    }
+};
+
+// Polls one exchange word until it carries `tag` (bit 7 of its low byte).
+// Returns 0 with the word in v, 1 if another workgroup raised the abort
+// word, 2 after spin_limit polls.
+__device__ __forceinline__ uint32_t await_word(const uint32_t *src,
+                                               uint32_t tag, uint32_t &v,
+                                               const uint32_t *abort,
+                                               uint32_t spin_limit)
 {
-    const uint32_t LS = G.LS(), TH = G.TH, TW = G.TW, dwr = TW >> 2;
-    const uint32_t sd = G.slot_dwords();
-    const uint32_t up = (ty + G.TY - 1) % G.TY, dn = (ty + 1) % G.TY;
-    const uint32_t lf = (tx + G.TX - 1) % G.TX, rt = (tx + 1) % G.TX;
-    auto slot = [&](uint32_t y, uint32_t x) {
-        return nb + (size_t)(2 * (y * G.TX + x) + s) * sd;
-    };
-    const uint32_t *sU = slot(up, tx), *sD = slot(dn, tx);
-    const uint32_t *sUL = slot(up, lf), *sUR = slot(up, rt);
-    const uint32_t *sDL = slot(dn, lf), *sDR = slot(dn, rt);
-    const uint32_t *sL = slot(ty, lf), *sR = slot(ty, rt);
-    // rows 0..3 from the bottom strips above, rows TH+4.. from top strips below
-    const uint32_t wdw = dwr + 4; // dwords per halo row: 2 + dwr + 2
-    for (uint32_t i = threadIdx.x; i < 8 * wdw; i += blockDim.x) {
-        const uint32_t h = i / wdw, j = i - h * wdw; // h: 0..3 top, 4..7 bottom
-        const uint32_t r = h & 3u;
-        const bool topside = h < 4;
-        const uint32_t lr = topside ? r : TH + 4 + r;
-        const uint32_t *mid = topside ? sU + TW : sD;      // bottom / top strip
-        const uint32_t *lft = topside ? sUL + TW : sDL;
-        const uint32_t *rgt = topside ? sUR + TW : sDR;
-        const uint32_t *src;
-        if (j < 2)
-            src = lft + r * dwr + dwr - 2 + j;
-        else if (j < dwr + 2)
-            src = mid + r * dwr + j - 2;
-        else
-            src = rgt + r * dwr + j - 2 - dwr;
-        const uint32_t v = xload(src);
-        *reinterpret_cast<uint32_t *>(lat + lr * LS + 4 * j) = v;
+    uint32_t spins = 0;
+    while ((v ^ tag) & 0x80u) {
+        if ((++spins & 63u) == 0) {
+            if (xload(abort))
+                return 1;
+            if (spins > spin_limit)
+                return 2;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        v = xload(src);
     }
-    // columns 0..7 and TW+8..TW+15 of rows 4..TH+3 from the side strips
-    for (uint32_t i = threadIdx.x; i < 4 * TH; i += blockDim.x) {
-        const uint32_t side = i / (2 * TH), q = i - side * 2 * TH;
-        const uint32_t r = q >> 1, j = q & 1u;
-        const uint32_t v = xload(side == 0 ? sL + 2 * TW + 2 * TH + q // right
-                                           : sR + 2 * TW + q);         // left
-        const uint32_t c = side == 0 ? 4 * j : TW + 8 + 4 * j;
-        *reinterpret_cast<uint32_t *>(lat + (4 + r) * LS + c) = v;
+    return 0;
+}
+
+// Rebuilds the halo from the neighbours' strips in slot `s` once they carry
+// `tag`.  Each thread keeps two words in flight; `between()` runs after the
+// first loads are issued and before they are awaited (every thread calls it
+// exactly once, so it may contain wave-wide operations), which hides the
+// load latency behind other work.  Returns the worst await_word status of
+// this thread (0 = all words arrived).
+template <class Fn>
+__device__ inline uint32_t tile_gather(uint8_t *lat, const uint32_t *nb,
+                                       const TileGeom &G, uint32_t ty,
+                                       uint32_t tx, uint32_t s, uint32_t tag,
+                                       const uint32_t *abort,
+                                       uint32_t spin_limit, Fn &&between)
+{
+    const HaloMap M(nb, G, ty, tx, s);
+    const uint32_t n = M.count(), bd = blockDim.x;
+    uint32_t i = threadIdx.x;
+    bool one = i < n, two = i + bd < n;
+    HaloWord a = M.at(one ? i : 0), b = M.at(two ? i + bd : 0);
+    uint32_t va = one ? xload(a.src) : 0u;
+    uint32_t vb = two ? xload(b.src) : 0u;
+    between();
+    uint32_t status = 0;
+    while (one) {
+        status = await_word(a.src, tag, va, abort, spin_limit);
+        if (!status && two)
+            status = await_word(b.src, tag, vb, abort, spin_limit);
+        if (status)
+            break;
+        *reinterpret_cast<uint32_t *>(lat + a.dst) = va & 0x7F7F7F7Fu;
+        if (two)
+            *reinterpret_cast<uint32_t *>(lat + b.dst) = vb & 0x7F7F7F7Fu;
+        i += 2 * bd;
+        one = i < n;
+        two = i + bd < n;
+        if (one) {
+            a = M.at(i);
+            va = xload(a.src);
+        }
+        if (two) {
+            b = M.at(i + bd);
+            vb = xload(b.src);
+        }
     }
+    return status;
+}
+
+__device__ inline uint32_t tile_gather(uint8_t *lat, const uint32_t *nb,
+                                       const TileGeom &G, uint32_t ty,
+                                       uint32_t tx, uint32_t s, uint32_t tag,
+                                       const uint32_t *abort,
+                                       uint32_t spin_limit)
+{
+    return tile_gather(lat, nb, G, ty, tx, s, tag, abort, spin_limit,
+                       [] {});
 }
 
 // Adds the interior's species counts into cnt[0..S] (LDS, zeroed).  SM == 8:
-// one-hot byte codes (values 0..7); else byte compares per species.
+// one-hot byte codes (values 0..7), two dwords per step (TW % 8 == 0 keeps
+// the pairs inside a row and 8-byte aligned); else byte compares per species.
+// A thread walks one column of pairs down the rows (rstep rows apart), so
+// its LDS address advances by a constant.
 template <int SM>
 __device__ __forceinline__ void tile_count(const uint8_t *lat,
                                            const TileGeom &G, uint32_t S,
                                            uint32_t *cnt)
 {
-    const uint32_t LS = G.LS(), dwr = G.TW >> 2, n = G.TH * dwr;
+    constexpr uint32_t per = SM == 8 ? 8u : 4u;
+    const uint32_t LS = G.LS(), dwr = G.TW / per;
+    const uint32_t rstep = blockDim.x / dwr; // >= 1: TW / 8 <= blockDim
+    const uint32_t r0 = threadIdx.x / dwr, j = threadIdx.x - r0 * dwr;
     uint32_t c[SM];
 #pragma unroll
     for (int s = 0; s < SM; ++s)
         c[s] = 0;
     uint32_t mine = 0;
-    uint32_t r = threadIdx.x / dwr, j = threadIdx.x - r * dwr;
-    const uint32_t dr = blockDim.x / dwr, dj = blockDim.x - dr * dwr;
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const uint32_t v = *reinterpret_cast<const uint32_t *>(
-            lat + (4 + r) * LS + 8 + 4 * j);
-        if (SM == 8) {
-            const uint32_t h = one_hot_bytes(v);
+    if (r0 < rstep) {
+        const uint8_t *p = lat + (4 + r0) * LS + 8 + per * j;
+        for (uint32_t r = r0; r < G.TH; r += rstep, p += rstep * LS) {
+            if constexpr (SM == 8) {
+                const uint2 v = *reinterpret_cast<const uint2 *>(p);
+                count_pair8(v.x, v.y, c);
+            } else {
+                const uint32_t v = *reinterpret_cast<const uint32_t *>(p);
+                ++mine;
 #pragma unroll
-            for (int s = 0; s < SM; ++s)
-                if ((uint32_t)s <= S)
-                    c[s] += __popc(h & (0x01010101u << s));
-        } else {
-            ++mine;
-#pragma unroll
-            for (int s = 0; s < SM; ++s)
-                if ((uint32_t)s <= S)
-                    c[s] += bytes_ne(v, (uint32_t)s);
-        }
-        j += dj;
-        r += dr;
-        if (j >= dwr) {
-            j -= dwr;
-            ++r;
+                for (int s = 0; s < SM; ++s)
+                    if ((uint32_t)s <= S)
+                        c[s] += bytes_ne(v, (uint32_t)s);
+            }
         }
     }
 #pragma unroll
