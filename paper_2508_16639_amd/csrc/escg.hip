@@ -460,10 +460,11 @@ __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
     tile_load(lat, a.lattice, G, ty, tx);
     setup_tables(TB, a.dom); // ends with a barrier
     const QuadCtx qc = make_quad_ctx(TB, a.T1, a.T2);
+    const TileWalk W = tile_walk(G, ty, tx);
 
     bool aborted = false;
     for (uint32_t t = 0; t < a.n_mcs; ++t) {
-        tile_mcs(lat, G, ty, tx, a.mcs0 + t, a.replica, k0, k1, qc);
+        tile_mcs(lat, G, W, a.mcs0 + t, a.replica, k0, k1, qc);
         // publish, count and gather touch disjoint parts of the region:
         // border strips and interior are read, only the halo is written
         const uint32_t e = t + 1, slot = exch_slot(e), tag = exch_tag(e);
@@ -538,7 +539,7 @@ __global__ __launch_bounds__(512) void tiled_step_kernel(StepArgs a)
     tile_load(lat, a.src, G, ty, tx);
     setup_tables(TB, a.dom);
     const QuadCtx qc = make_quad_ctx(TB, a.T1, a.T2);
-    tile_mcs(lat, G, ty, tx, a.t, a.replica, (uint32_t)a.seed,
+    tile_mcs(lat, G, tile_walk(G, ty, tx), a.t, a.replica, (uint32_t)a.seed,
              (uint32_t)(a.seed >> 32), qc);
     tile_store(lat, a.dst, G, ty, tx);
     if (a.counts) {
@@ -896,11 +897,15 @@ struct TiledPlan {
     size_t lds = 0;
 };
 
-uint32_t tiled_threads(const TileGeom &G)
+// Workgroup size for a tile (0: the tile is too wide): see tile_threads;
+// tile_count walks one column of dword pairs per thread, so TW / 8 threads
+// are needed (TW / 4 for S > 7).
+uint32_t tiled_threads(const TileGeom &G, uint32_t cap)
 {
-    const uint32_t items = (G.RH() / 2) * ((G.TW + 16) / 8);
-    uint32_t nt = (items + 63) / 64 * 64;
-    return std::min(1024u, std::max(64u, nt));
+    const uint32_t nt = std::max(64u, tile_threads(G, cap));
+    if (tile_threads(G, cap) == 0 || G.TW / 4 > nt)
+        return 0;
+    return nt;
 }
 
 std::atomic<uint32_t> g_tiled_min_L{400};
@@ -949,8 +954,8 @@ TiledPlan plan_tiled_uncached(uint32_t L, uint32_t S)
             const size_t lds = G.region_bytes();
             if (lds + static_lds_bytes(S) + 64 > lds_max)
                 continue;
-            const uint32_t nt = tiled_threads(G);
-            if (G.TW / 4 > nt) // tile_count walks one column per thread
+            const uint32_t nt = tiled_threads(G, 1024);
+            if (nt == 0)
                 continue;
             const void *fn = S <= 7 ? (const void *)tiled_persistent_kernel<true>
                                     : (const void *)tiled_persistent_kernel<false>;
@@ -1023,6 +1028,8 @@ TiledPlan plan_step_uncached(uint32_t L, uint32_t S)
             const size_t lds = G.region_bytes();
             if (lds + static_lds_bytes(S) + 64 > lds_max)
                 continue;
+            if (tiled_threads(G, 512) == 0)
+                continue;
             const double T = (double)G.TY * G.TX;
             const double area = (double)(TH + 8) * (TW + 16);
             // work per CU, rounded up to whole tiles, plus a fixed cost per
@@ -1033,7 +1040,7 @@ TiledPlan plan_step_uncached(uint32_t L, uint32_t S)
                 best_cost = cost;
                 best.ok = true;
                 best.G = G;
-                best.threads = std::min(512u, tiled_threads(G));
+                best.threads = tiled_threads(G, 512);
                 best.lds = lds;
             }
         }

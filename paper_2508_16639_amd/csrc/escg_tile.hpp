@@ -68,47 +68,103 @@ __device__ inline void tile_store(const uint8_t *lat, uint8_t *g,
     }
 }
 
+// A thread's share of the region's quads, fixed for the whole run: one quad
+// column js and the block rows r0, r0 + rstep, ... .  The global block row
+// of LDS block row k is R0/2 - 2 + k (mod L/2) and the global quad column
+// of js is g0/8 - 1 + js (mod L/8), for either offset, so the Philox counter
+// word c0 = by * Q + qx of the first quad and its LDS offset advance by
+// constants (one wrap test for c0 because rstep <= L/2).
+struct TileWalk {
+    uint32_t c0;     // counter word of the first quad
+    uint32_t pa0;    // LDS offset of its top row for oy = 0
+    uint32_t r0;     // first block row
+    uint32_t rstep;  // block rows per step
+    uint32_t cstep;  // rstep * Q
+    uint32_t pstep;  // 2 * rstep * LS
+    uint32_t wrap;   // (L/2) * Q counter words per pass
+    bool active;
+};
+
+__device__ inline TileWalk tile_walk(const TileGeom &G, uint32_t ty,
+                                     uint32_t tx)
+{
+    const uint32_t L = G.L, LS = G.LS(), Q = L >> 3, Lb = L >> 1;
+    const uint32_t NJ = (G.TW + 16) >> 3; // quads per block row
+    TileWalk W;
+    W.rstep = min(blockDim.x / NJ, Lb);
+    W.r0 = threadIdx.x / NJ;
+    const uint32_t js = threadIdx.x - W.r0 * NJ;
+    W.active = W.r0 < W.rstep;
+    const uint32_t qx = ((tx * G.TW) / 8 + Q - 1 + js) % Q;
+    const uint32_t by = ((ty * G.TH) / 2 + Lb - 2 + W.r0) % Lb;
+    W.c0 = by * Q + qx;
+    W.pa0 = 2 * W.r0 * LS + 8 * js;
+    W.cstep = W.rstep * Q;
+    W.pstep = 2 * W.rstep * LS;
+    W.wrap = Lb * Q;
+    return W;
+}
+
+// Threads for a tile: enough quad columns times rows per step that the
+// block rows split into equal numbers of steps (at most 1024).
+__host__ __device__ inline uint32_t tile_threads(const TileGeom &G,
+                                                 uint32_t cap)
+{
+    const uint32_t NJ = (G.TW + 16) >> 3, nbr = G.RH() >> 1;
+    uint32_t maxr = cap / NJ;
+    if (maxr == 0)
+        return 0;
+    const uint32_t steps = (nbr + maxr - 1) / maxr;
+    const uint32_t rows = (nbr + steps - 1) / steps;
+    const uint32_t nt = (rows * NJ + 63) / 64 * 64;
+    return nt < cap ? nt : cap;
+}
+
+// Pass p of MCS t for this thread's quads; w = word p of the MCS's offset
+// draw (ox = bit 0, oy = bit 1, uniform).
+__device__ __forceinline__ void tile_pass(uint8_t *lat, const TileGeom &G,
+                                          const TileWalk &W, uint32_t w,
+                                          uint32_t p, uint32_t t,
+                                          uint32_t replica, uint32_t k0,
+                                          uint32_t k1, const QuadCtx &qc)
+{
+    const uint32_t LS = G.LS();
+    const uint32_t ox = w & 1u, oy = (w >> 1) & 1u;
+    const uint32_t nbr = (G.RH() - oy) >> 1;
+    const uint32_t ctr2 = (kTagPass << 8) | p;
+    if (!W.active)
+        return;
+    uint32_t c0 = W.c0, pa = W.pa0 + oy * LS;
+    if (ox == 0) {
+        for (uint32_t k = W.r0; k < nbr; k += W.rstep) {
+            const Words r = philox10(c0, t, ctr2, replica, k0, k1);
+            quad_even(lat, pa, pa + LS, r, qc);
+            pa += W.pstep;
+            c0 += W.cstep;
+            c0 = min(c0, c0 - W.wrap);
+        }
+    } else {
+        for (uint32_t k = W.r0; k < nbr; k += W.rstep) {
+            const Words r = philox10(c0, t, ctr2, replica, k0, k1);
+            quad_odd(lat, pa, pa + LS, pa + 8, pa + LS + 8, r, qc);
+            pa += W.pstep;
+            c0 += W.cstep;
+            c0 = min(c0, c0 - W.wrap);
+        }
+    }
+}
+
 // One MCS over the region: all quads of all block rows, four passes.
 __device__ __forceinline__ void tile_mcs(uint8_t *lat, const TileGeom &G,
-                                         uint32_t ty, uint32_t tx, uint32_t t,
+                                         const TileWalk &W, uint32_t t,
                                          uint32_t replica, uint32_t k0,
                                          uint32_t k1, const QuadCtx &qc)
 {
-    const uint32_t L = G.L, LS = G.LS(), Q = L >> 3, Lb = L >> 1;
-    const uint32_t NJ = (G.TW + 16) >> 3;        // quads per block row
-    const uint32_t qbase = (tx * G.TW) / 8 + Q - 1; // global quad of js = 0
-    // global block row of LDS block row k is R0/2 - 2 + k (mod L/2)
-    const uint32_t bybase = (ty * G.TH) / 2 + Lb - 2;
     const Words off = philox10(0u, t, kTagOffset << 8, replica, k0, k1);
 #pragma unroll
     for (uint32_t p = 0; p < 4; ++p) {
-        const uint32_t ox = off.w[p] & 1u, oy = (off.w[p] >> 1) & 1u;
-        const uint32_t nbr = (G.RH() - oy) >> 1;
-        const uint32_t ctr2 = (kTagPass << 8) | p;
-        const uint32_t items = nbr * NJ;
-        uint32_t k = threadIdx.x / NJ, js = threadIdx.x - k * NJ;
-        const uint32_t dk = blockDim.x / NJ, djs = blockDim.x - dk * NJ;
-        for (uint32_t i = threadIdx.x; i < items; i += blockDim.x) {
-            const uint32_t lr = oy + 2 * k;
-            uint32_t by = bybase + k;
-            by -= (by >= Lb) ? Lb : 0u;
-            by -= (by >= Lb) ? Lb : 0u;
-            uint32_t qx = qbase + js;
-            qx -= (qx >= Q) ? Q : 0u;
-            qx -= (qx >= Q) ? Q : 0u;
-            const Words r = philox10(by * Q + qx, t, ctr2, replica, k0, k1);
-            const uint32_t pa = lr * LS + 8 * js, pc = pa + LS;
-            if (ox == 0)
-                quad_even(lat, pa, pc, r, qc);
-            else
-                quad_odd(lat, pa, pc, pa + 8, pc + 8, r, qc);
-            js += djs;
-            k += dk;
-            if (js >= NJ) {
-                js -= NJ;
-                ++k;
-            }
-        }
+        tile_pass(lat, G, W, __builtin_amdgcn_readfirstlane(off.w[p]), p, t,
+                  replica, k0, k1, qc);
         __syncthreads();
     }
 }
