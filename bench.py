@@ -178,7 +178,7 @@ def serving(args, torch, escg, workloads):
 def cpu_baseline(w):
     import numpy as np
     import oracle as O
-    n = 25
+    n = 50
     job = O.Job(w.L, w.S, O.circulant_matrix(w.S, w.K), w.ex, w.sel, w.rep,
                 seed=w.seed, replica=w.replica)
     t0 = time.perf_counter()

@@ -83,10 +83,18 @@ __device__ __forceinline__ void count_dwords(const uint32_t *lat32,
     if constexpr (SM == 8) {
         // ndw is even (rows are padded to a multiple of 8 bytes)
         const uint2 *lat64 = reinterpret_cast<const uint2 *>(lat32);
-        for (uint32_t i = threadIdx.x; i < (ndw >> 1); i += blockDim.x) {
-            const uint2 v = lat64[i];
-            count_pair8(v.x, v.y, c);
-        }
+        auto walk = [&](auto ns) {
+            for (uint32_t i = threadIdx.x; i < (ndw >> 1); i += blockDim.x) {
+                const uint2 v = lat64[i];
+                count_pair8<decltype(ns)::value>(v.x, v.y, c);
+            }
+        };
+        if (S < 4)
+            walk(std::integral_constant<int, 4>{});
+        else if (S < 6)
+            walk(std::integral_constant<int, 6>{});
+        else
+            walk(std::integral_constant<int, 8>{});
     } else {
         for (uint32_t i = threadIdx.x; i < ndw; i += blockDim.x) {
             const uint32_t v = lat32[i];

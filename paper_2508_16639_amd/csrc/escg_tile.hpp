@@ -21,6 +21,8 @@
 
 #include "escg_quad.hpp"
 
+#include <type_traits>
+
 namespace escg {
 
 struct TileGeom {
@@ -387,12 +389,25 @@ __device__ __forceinline__ void tile_count(const uint8_t *lat,
         c[s] = 0;
     uint32_t mine = 0;
     if (r0 < rstep) {
-        const uint8_t *p = lat + (4 + r0) * LS + 8 + per * j;
-        for (uint32_t r = r0; r < G.TH; r += rstep, p += rstep * LS) {
-            if constexpr (SM == 8) {
-                const uint2 v = *reinterpret_cast<const uint2 *>(p);
-                count_pair8(v.x, v.y, c);
-            } else {
+        const uint8_t *p0 = lat + (4 + r0) * LS + 8 + per * j;
+        if constexpr (SM == 8) {
+            // one loop per species range: absent species cost nothing
+            auto walk = [&](auto ns) {
+                const uint8_t *p = p0;
+                for (uint32_t r = r0; r < G.TH; r += rstep, p += rstep * LS) {
+                    const uint2 v = *reinterpret_cast<const uint2 *>(p);
+                    count_pair8<decltype(ns)::value>(v.x, v.y, c);
+                }
+            };
+            if (S < 4)
+                walk(std::integral_constant<int, 4>{});
+            else if (S < 6)
+                walk(std::integral_constant<int, 6>{});
+            else
+                walk(std::integral_constant<int, 8>{});
+        } else {
+            const uint8_t *p = p0;
+            for (uint32_t r = r0; r < G.TH; r += rstep, p += rstep * LS) {
                 const uint32_t v = *reinterpret_cast<const uint32_t *>(p);
                 ++mine;
 #pragma unroll
