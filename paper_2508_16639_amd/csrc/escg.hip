@@ -162,9 +162,7 @@ __device__ void run_job_lds(const JobDev &J, uint8_t *base, uint8_t *smem,
     }
     __syncthreads();
     const QuadCtx qc = make_quad_ctx(TB, J.T1, J.T2);
-    const uint32_t Lb = L >> 1, Q = (Lb + 3) >> 2;
-    const uint32_t by0 = tid / Q, qx0 = tid - by0 * Q;
-    const uint32_t dby = nt / Q, dqx = nt - dby * Q;
+    const LdsWalk W = lds_walk(L, LS);
     const uint32_t ndw = (LS * L) >> 2;
 
     uint32_t cur = 0;
@@ -181,8 +179,7 @@ __device__ void run_job_lds(const JobDev &J, uint8_t *base, uint8_t *smem,
         const uint32_t nxt = cur ^ 1u;
         if (tid < 32)
             s_cnt[nxt * 32 + tid] = 0;
-        lds_mcs(lat, L, LS, J.mcs0 + t, J.replica, k0, k1, qc, by0, qx0, dby,
-                dqx);
+        lds_mcs(lat, L, LS, J.mcs0 + t, J.replica, k0, k1, qc, W);
         if (kPacked)
             count_dwords<8>(lat32, ndw, S, s_cnt + nxt * 32);
         else

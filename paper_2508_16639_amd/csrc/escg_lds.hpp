@@ -33,55 +33,89 @@ __host__ __device__ inline uint32_t row_stride(uint32_t L)
     return (L + 7) & ~7u;
 }
 
+// A thread's share of the quads of a lattice held whole in LDS, fixed for
+// the job: one quad column qx (Q = ceil(L/8) quads per block row) and the
+// block rows by0, by0 + rstep, ... < L/2.  The quad's Philox counter word
+// is by * Q + qx, so it and the LDS offset advance by constants.
+struct LdsWalk {
+    uint32_t by0, rstep;
+    uint32_t c0, cstep;   // counter word of the first quad, rstep * Q
+    uint32_t pa0, pstep;  // LDS offset of the first quad's top row (oy = 0)
+    uint32_t col;         // first byte of the quad in its row: 8 * qx
+    uint32_t dnext;       // (column after the quad, wrapped) - col, mod 2^32
+    bool active, full;    // full: four blocks (else the row's last quad)
+};
+
+__device__ inline LdsWalk lds_walk(uint32_t L, uint32_t LS)
+{
+    const uint32_t Lb = L >> 1, Q = (Lb + 3) >> 2;
+    LdsWalk W;
+    W.rstep = min(blockDim.x / Q, Lb);
+    W.by0 = threadIdx.x / Q;
+    const uint32_t qx = threadIdx.x - W.by0 * Q;
+    W.active = W.by0 < W.rstep;
+    W.full = 4u * qx + 4u <= Lb;
+    W.col = 8u * qx;
+    W.dnext = ((W.col + 8u == L) ? 0u : W.col + 8u) - W.col;
+    W.c0 = W.by0 * Q + qx;
+    W.cstep = W.rstep * Q;
+    W.pa0 = 2u * W.by0 * LS + W.col;
+    W.pstep = 2u * W.rstep * LS;
+    return W;
+}
+
+// Pass p of MCS t for this thread's quads; w = word p of the MCS's offset
+// draw (ox = bit 0, oy = bit 1, uniform).
+__device__ __forceinline__ void lds_pass(uint8_t *lat, uint32_t L,
+                                         uint32_t LS, const LdsWalk &W,
+                                         uint32_t w, uint32_t p, uint32_t t,
+                                         uint32_t replica, uint32_t k0,
+                                         uint32_t k1, const QuadCtx &qc)
+{
+    const uint32_t Lb = L >> 1;
+    const uint32_t ox = w & 1u, oy = (w >> 1) & 1u;
+    const uint32_t ctr2 = (kTagPass << 8) | p;
+    if (!W.active)
+        return;
+    uint32_t c0 = W.c0, pa = W.pa0 + oy * LS;
+    for (uint32_t by = W.by0; by < Lb; by += W.rstep) {
+        const Words r = philox10(c0, t, ctr2, replica, k0, k1);
+        // the bottom row of the last block row wraps to row 0
+        const uint32_t pc = (oy && by == Lb - 1u) ? W.col : pa + LS;
+        if (W.full) {
+            if (ox == 0)
+                quad_even(lat, pa, pc, r, qc);
+            else
+                quad_odd(lat, pa, pc, pa + W.dnext, pc + W.dnext, r, qc);
+        } else {
+            // last quad of a row with fewer than four blocks
+            const uint32_t rowA = pa - W.col, rowC = pc - W.col;
+            for (uint32_t j = 0; j < 4; ++j) {
+                if (W.col / 2u + j < Lb) {
+                    const uint32_t x0 = W.col + 2u * j + ox;
+                    const uint32_t x1 = (x0 + 1u == L) ? 0u : x0 + 1u;
+                    block_bytes(lat, rowA + x0, rowA + x1, rowC + x0,
+                                rowC + x1, pick(r, j), qc);
+                }
+            }
+        }
+        pa += W.pstep;
+        c0 += W.cstep;
+    }
+}
+
 // One MCS (four passes) on an L x L lattice held whole in LDS with row
-// stride LS.  Work item = one quad (by, qx); the quad's Philox counter is
-// by*Q + qx, the index of the work item.
+// stride LS.
 __device__ __forceinline__ void lds_mcs(uint8_t *lat, uint32_t L, uint32_t LS,
                                         uint32_t t, uint32_t replica,
                                         uint32_t k0, uint32_t k1,
-                                        const QuadCtx &qc, uint32_t by0,
-                                        uint32_t qx0, uint32_t dby,
-                                        uint32_t dqx)
+                                        const QuadCtx &qc, const LdsWalk &W)
 {
-    const uint32_t Lb = L >> 1, Q = (Lb + 3) >> 2, nq = Lb * Q;
     const Words off = philox10(0u, t, kTagOffset << 8, replica, k0, k1);
 #pragma unroll
     for (uint32_t p = 0; p < 4; ++p) {
-        const uint32_t ox = off.w[p] & 1u, oy = (off.w[p] >> 1) & 1u;
-        const uint32_t ctr2 = (kTagPass << 8) | p;
-        uint32_t by = by0, qx = qx0;
-        for (uint32_t qi = threadIdx.x; qi < nq; qi += blockDim.x) {
-            const Words r = philox10(qi, t, ctr2, replica, k0, k1);
-            const uint32_t r0 = 2u * by + oy;
-            const uint32_t r1 = (r0 + 1u == L) ? 0u : r0 + 1u;
-            const uint32_t rowA = r0 * LS, rowC = r1 * LS;
-            const uint32_t col = 8u * qx;
-            if (4u * qx + 4u <= Lb) {
-                if (ox == 0) {
-                    quad_even(lat, rowA + col, rowC + col, r, qc);
-                } else {
-                    const uint32_t e = (col + 8u == L) ? 0u : col + 8u;
-                    quad_odd(lat, rowA + col, rowC + col, rowA + e, rowC + e,
-                             r, qc);
-                }
-            } else {
-                // last quad of a row with fewer than four blocks
-                for (uint32_t j = 0; j < 4; ++j) {
-                    if (4u * qx + j < Lb) {
-                        const uint32_t c0 = col + 2u * j + ox;
-                        const uint32_t c1 = (c0 + 1u == L) ? 0u : c0 + 1u;
-                        block_bytes(lat, rowA + c0, rowA + c1, rowC + c0,
-                                    rowC + c1, pick(r, j), qc);
-                    }
-                }
-            }
-            qx += dqx;
-            by += dby;
-            if (qx >= Q) {
-                qx -= Q;
-                ++by;
-            }
-        }
+        lds_pass(lat, L, LS, W, __builtin_amdgcn_readfirstlane(off.w[p]), p,
+                 t, replica, k0, k1, qc);
         __syncthreads();
     }
 }
