@@ -102,6 +102,15 @@ escg_status escg_circulant_dom(uint32_t S, uint32_t kmask, uint32_t *h_dom);
 escg_status escg_dom_from_matrix(uint32_t S, const uint8_t *h_D,
                                  uint32_t *h_dom);
 
+/* Exchange rate for mobility M on an L x L lattice: *eps = M * L * L / 2,
+ * i.e. M = 2 eps / N with N = L * L sites, the convention of the cited
+ * three-species mobility study whose results the paper replicates (Sec.
+ * "Extending Current Literature").  The paper's own rate listing (Sec.
+ * "Single Threaded ESCG in C++") writes eps = 2 M N, a factor of four away;
+ * the library keeps its reading in this one function.  EINVAL if M is
+ * negative or not finite, L is 0, or eps is NULL.  Host only. */
+escg_status escg_eps_from_mobility(double M, uint32_t L, double *eps);
+
 /* The two 24-bit action thresholds of the job: an elementary step with
  * uniform 24-bit draw u is an exchange if u < T1, a selection if
  * T1 <= u < T2, else a reproduction, where (in IEEE double, this order)
@@ -174,6 +183,25 @@ escg_status escg_batch_run(uint32_t n, const escg_params *h_params,
                            const uint32_t *h_mcs0, const uint32_t *h_max_mcs,
                            uint32_t mode, uint32_t init, uint32_t *d_results,
                            void *stream);
+
+/* Advances n independent jobs, job j by h_n_mcs[j] MCS from absolute MCS
+ * h_mcs0[j], with one launch per MCS for all jobs together: the tiles of
+ * every job still running form one grid, so lattices too small to fill the
+ * GPU on their own share it.  This is the step of the paper's overall loop
+ * (Algorithm "Overall ESCG Loop", N elementary steps per MCS) for a set of
+ * simulations at once; each job's result equals escg_step_mcs on that job
+ * alone, byte for byte.
+ *   h_params[n]      job parameters; every L must be a multiple of 8 and
+ *                    >= 16 (ESCG_EUNSUPPORTED otherwise, nothing enqueued,
+ *                    escg_last_error() names the job)
+ *   h_lattices[n]    device pointers to each job's uint8[L*L] lattice,
+ *                    4-byte aligned, pairwise disjoint, updated in place
+ *   h_mcs0[n], h_n_mcs[n]  start MCS and number of MCS per job (0: untouched)
+ * No counts are recorded (escg_densities reads a lattice afterwards).
+ * Scratch: one ping-pong lattice per job, stream-ordered. */
+escg_status escg_step_batch(uint32_t n, const escg_params *h_params,
+                            uint8_t *const *h_lattices, const uint32_t *h_mcs0,
+                            const uint32_t *h_n_mcs, void *stream);
 
 /* Single-job routing knob: escg_step_mcs keeps a lattice with
  * L <= min(L_max, escg_batch_max_L()) whole in one workgroup's LDS and sends

@@ -558,6 +558,53 @@ __global__ __launch_bounds__(512) void tiled_step_kernel(StepArgs a)
     }
 }
 
+// One MCS of many large lattices per launch: the tiles of every job form one
+// grid (job i owns workgroups [wg0_i, wg0_{i+1})), so jobs too small to fill
+// the GPU alone advance together.  Each job ping-pongs between its lattice
+// and a scratch buffer: step k reads the lattice when k is even.
+struct BatchStepJob {
+    uint8_t *lattice;
+    uint8_t *scratch;
+    uint64_t seed;
+    TileGeom G;
+    uint32_t S, T1, T2, replica, t0;
+    uint32_t wg0;
+    uint32_t dom[32];
+};
+
+constexpr uint32_t kBatchStepThreads = 512;
+
+template <bool kPacked>
+__global__ __launch_bounds__(kBatchStepThreads) void tiled_step_batch_kernel(
+    const BatchStepJob *jobs, uint32_t njobs, uint32_t k)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ LdsTables<kPacked ? 8 : 32> TB;
+    // the job owning this workgroup: last i with wg0_i <= blockIdx.x
+    const uint32_t b = blockIdx.x;
+    uint32_t lo = 0, hi = njobs;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (jobs[mid].wg0 <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const BatchStepJob &J = jobs[lo];
+    const TileGeom G = J.G;
+    const uint32_t tile = b - J.wg0, ty = tile / G.TX, tx = tile - ty * G.TX;
+    const uint8_t *src = (k & 1u) ? J.scratch : J.lattice;
+    uint8_t *dst = (k & 1u) ? J.lattice : J.scratch;
+    uint8_t *lat = smem;
+    tile_load(lat, src, G, ty, tx);
+    setup_tables(TB, J.dom);
+    const QuadCtx qc = make_quad_ctx(TB, J.T1, J.T2);
+    tile_mcs(lat, G, tile_walk(G, ty, tx), J.t0 + k, J.replica,
+             (uint32_t)J.seed, (uint32_t)(J.seed >> 32), qc);
+    tile_store(lat, dst, G, ty, tx);
+}
+
+
 // ---------------------------------------------------------------------------
 // Small kernels
 // ---------------------------------------------------------------------------
@@ -1219,6 +1266,14 @@ escg_status escg_dom_from_matrix(uint32_t S, const uint8_t *h_D,
     return ESCG_OK;
 }
 
+escg_status escg_eps_from_mobility(double M, uint32_t L, double *eps)
+{
+    if (!eps || L == 0 || !(M >= 0) || !std::isfinite(M))
+        return ESCG_EINVAL;
+    *eps = M * (double)L * (double)L / 2.0;
+    return ESCG_OK;
+}
+
 escg_status escg_thresholds(const escg_params *p, uint32_t *T1, uint32_t *T2)
 {
     if (!p || !T1 || !T2)
@@ -1477,6 +1532,125 @@ escg_status escg_async_status(int reset)
             return last_hip(hipGetLastError());
     }
     return v ? ESCG_ETIMEOUT : ESCG_OK;
+}
+
+escg_status escg_step_batch(uint32_t n, const escg_params *h_params,
+                            uint8_t *const *h_lattices, const uint32_t *h_mcs0,
+                            const uint32_t *h_n_mcs, void *stream)
+{
+    if (n == 0)
+        return ESCG_OK;
+    if (!h_params || !h_lattices || !h_mcs0 || !h_n_mcs)
+        return ESCG_EINVAL;
+    std::vector<TiledPlan> plans(n);
+    std::vector<std::pair<uintptr_t, uintptr_t>> spans(n);
+    for (uint32_t j = 0; j < n; ++j) {
+        const escg_params *p = &h_params[j];
+        escg_status s = validate(p);
+        if (s != ESCG_OK)
+            return s;
+        if (!h_lattices[j] || !aligned4(h_lattices[j]))
+            return ESCG_EINVAL;
+        plans[j] = plan_step(p->L, p->S);
+        if (!plans[j].ok) {
+            std::snprintf(g_last_error, sizeof(g_last_error),
+                          "job %u: L = %u has no tile plan (needs L %% 8 == 0, "
+                          "L >= 16)", j, p->L);
+            return ESCG_EUNSUPPORTED;
+        }
+        const uintptr_t a = reinterpret_cast<uintptr_t>(h_lattices[j]);
+        spans[j] = {a, a + (uintptr_t)p->L * p->L};
+    }
+    std::sort(spans.begin(), spans.end());
+    for (uint32_t j = 1; j < n; ++j)
+        if (spans[j].first < spans[j - 1].second)
+            return ESCG_EINVAL; // lattices overlap
+    hipStream_t st = S_(stream);
+    for (int packed = 1; packed >= 0; --packed) {
+        // jobs of this kernel instantiation, longest chunk first, so the jobs
+        // still running at step k are a prefix of the table
+        std::vector<uint32_t> idx;
+        for (uint32_t j = 0; j < n; ++j)
+            if ((h_params[j].S <= 7) == (packed == 1) && h_n_mcs[j] > 0)
+                idx.push_back(j);
+        if (idx.empty())
+            continue;
+        std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) {
+            return h_n_mcs[a] > h_n_mcs[b];
+        });
+        const uint32_t m = (uint32_t)idx.size();
+        std::vector<BatchStepJob> tbl(m);
+        std::vector<uint32_t> wg_end(m);
+        size_t scratch_bytes = 0, lds = 0;
+        uint32_t wg = 0;
+        for (uint32_t i = 0; i < m; ++i) {
+            const uint32_t j = idx[i];
+            const escg_params *p = &h_params[j];
+            const Derived d = derive(p);
+            BatchStepJob &J = tbl[i];
+            std::memset(&J, 0, sizeof(J));
+            J.lattice = h_lattices[j];
+            J.seed = p->seed;
+            J.G = plans[j].G;
+            J.S = p->S;
+            J.T1 = d.T1;
+            J.T2 = d.T2;
+            J.replica = p->replica;
+            J.t0 = h_mcs0[j];
+            J.wg0 = wg;
+            for (int q = 0; q < 32; ++q)
+                J.dom[q] = p->dom[q];
+            wg += J.G.TY * J.G.TX;
+            wg_end[i] = wg;
+            scratch_bytes += ((size_t)p->L * p->L + 255) & ~(size_t)255;
+            lds = std::max(lds, plans[j].lds);
+        }
+        const size_t tbl_bytes = (sizeof(BatchStepJob) * m + 255) & ~(size_t)255;
+        uint8_t *dev = nullptr;
+        if (hipMallocAsync((void **)&dev, tbl_bytes + scratch_bytes, st) !=
+            hipSuccess)
+            return ESCG_ENOMEM;
+        size_t off = tbl_bytes;
+        for (uint32_t i = 0; i < m; ++i) {
+            tbl[i].scratch = dev + off;
+            off += ((size_t)tbl[i].G.L * tbl[i].G.L + 255) & ~(size_t)255;
+        }
+        BatchStepJob *d_tbl = reinterpret_cast<BatchStepJob *>(dev);
+        if (hipMemcpyAsync(d_tbl, tbl.data(), sizeof(BatchStepJob) * m,
+                           hipMemcpyHostToDevice, st) != hipSuccess) {
+            (void)hipFreeAsync(dev, st);
+            return ESCG_EDEVICE;
+        }
+        const void *fn = packed ? (const void *)tiled_step_batch_kernel<true>
+                                : (const void *)tiled_step_batch_kernel<false>;
+        allow_dynamic_lds(fn, lds);
+        uint32_t active = m;
+        const uint32_t steps = h_n_mcs[idx[0]];
+        for (uint32_t k = 0; k < steps; ++k) {
+            while (active > 0 && h_n_mcs[idx[active - 1]] <= k)
+                --active;
+            const uint32_t grid = wg_end[active - 1];
+            if (packed)
+                hipLaunchKernelGGL(tiled_step_batch_kernel<true>, dim3(grid),
+                                   dim3(kBatchStepThreads), lds, st, d_tbl,
+                                   active, k);
+            else
+                hipLaunchKernelGGL(tiled_step_batch_kernel<false>, dim3(grid),
+                                   dim3(kBatchStepThreads), lds, st, d_tbl,
+                                   active, k);
+        }
+        // an odd number of steps leaves the state in the scratch buffer
+        for (uint32_t i = 0; i < m; ++i)
+            if (h_n_mcs[idx[i]] & 1u)
+                launch_copy(tbl[i].lattice, tbl[i].scratch,
+                            (size_t)tbl[i].G.L * tbl[i].G.L, st);
+        escg_status s = last_hip(hipGetLastError());
+        (void)hipFreeAsync(dev, st);
+        if (s != ESCG_OK)
+            return s;
+    }
+    g_last_route = ESCG_ROUTE_TILED;
+    return ESCG_OK;
 }
 
 escg_status escg_batch_run(uint32_t n, const escg_params *h_params,

@@ -44,8 +44,9 @@ class CParams(C.Structure):
 
 
 EXPORTS = ("escg_status_str", "escg_last_error", "escg_circulant_dom", "escg_dom_from_matrix",
-           "escg_thresholds", "escg_init", "escg_densities", "escg_step_mcs",
+           "escg_thresholds", "escg_eps_from_mobility", "escg_init", "escg_densities", "escg_step_mcs",
            "escg_run_until_extinction", "escg_batch_max_L", "escg_batch_run",
+           "escg_step_batch",
            "escg_set_single_lds_max_L", "escg_set_persistent_min_L",
            "escg_async_status", "escg_last_route", "escg_set_tile_shape",
            "escg_tile_plan")
@@ -78,6 +79,8 @@ def lib():
     L.escg_circulant_dom.argtypes = [u32, u32, u32p]
     L.escg_dom_from_matrix.argtypes = [u32, C.POINTER(C.c_uint8), u32p]
     L.escg_thresholds.argtypes = [P, u32p, u32p]
+    L.escg_eps_from_mobility.argtypes = [C.c_double, u32,
+                                         C.POINTER(C.c_double)]
     L.escg_init.argtypes = [P, vp, vp]
     L.escg_densities.argtypes = [P, vp, vp, vp]
     L.escg_step_mcs.argtypes = [P, vp, u32, u32, vp, vp]
@@ -86,6 +89,8 @@ def lib():
     L.escg_batch_max_L.restype = u32
     L.escg_batch_run.argtypes = [u32, P, C.POINTER(C.c_uint64), vp,
                                  u32p, u32p, u32, u32, vp, vp]
+    L.escg_step_batch.argtypes = [u32, P, C.POINTER(C.c_void_p), u32p,
+                                  u32p, vp]
     L.escg_set_single_lds_max_L.argtypes = [u32]
     L.escg_set_persistent_min_L.argtypes = [u32]
     L.escg_async_status.argtypes = [C.c_int]
@@ -165,6 +170,15 @@ def thresholds(p: Params):
     _check(lib().escg_thresholds(C.byref(cp), C.byref(t1), C.byref(t2)),
            "escg_thresholds")
     return t1.value, t2.value
+
+
+def eps_from_mobility(M: float, L: int) -> float:
+    """Exchange rate for mobility M on an L x L lattice (M = 2 eps / L^2),
+    computed by the library."""
+    e = C.c_double()
+    _check(lib().escg_eps_from_mobility(float(M), int(L), C.byref(e)),
+           "escg_eps_from_mobility")
+    return e.value
 
 
 def batch_max_L(S: int = 3) -> int:
@@ -299,3 +313,23 @@ def batch_run(params: Sequence[Params], offsets, lattices, max_mcs,
         1 if init_lattices else 0,
         _ptr(results, "torch.int32", n * BATCH_RESULT_WORDS),
         _stream(stream)), "escg_batch_run")
+
+
+def step_batch(params: Sequence[Params], lattices, mcs0, n_mcs,
+               stream=None) -> None:
+    """Advances each job i (``lattices[i]``: its uint8 device tensor of
+    L*L sites) by ``n_mcs[i]`` MCS from MCS ``mcs0[i]``, all jobs together,
+    one launch per MCS.  Every L must be a multiple of 8 (>= 16)."""
+    n = len(params)
+    assert len(lattices) == n and len(mcs0) == n and len(n_mcs) == n
+    arr = (CParams * max(n, 1))()
+    ptrs = (C.c_void_p * max(n, 1))()
+    for i, (p, t) in enumerate(zip(params, lattices)):
+        arr[i] = p.c()
+        ptrs[i] = _ptr(t, "torch.uint8", p.L * p.L).value
+    m0 = np.ascontiguousarray(mcs0, dtype=np.uint32)
+    nm = np.ascontiguousarray(n_mcs, dtype=np.uint32)
+    _check(lib().escg_step_batch(
+        n, arr, ptrs, m0.ctypes.data_as(C.POINTER(C.c_uint32)),
+        nm.ctypes.data_as(C.POINTER(C.c_uint32)), _stream(stream)),
+        "escg_step_batch")

@@ -10,8 +10,9 @@ arrive while an iteration runs join at the next iteration boundary.
 
 Work within an iteration overlaps on the device: all active jobs small
 enough for one workgroup's LDS advance together in one persistent batched
-launch (one workgroup per job), while larger jobs advance with per-MCS tiled
-launches on their own streams at the same time.  Because every random draw
+launch (one workgroup per job), while the larger jobs advance together on a
+second stream with one tiled launch per MCS whose grid holds the tiles of
+all of them.  Because every random draw
 is keyed by (seed, replica, MCS, pass, site), a job's result does not depend
 on its co-runners, on chunking or on admission time: it is byte-identical to
 the job run alone.
@@ -241,8 +242,22 @@ class DeviceExecutor:
                 ev.record()
                 done.append(ev)
             self._res = res  # alive until the iteration completes
-        for i, (h, r, m0, n) in enumerate(large):
-            s = self.streams[i % len(self.streams)]
+        # large jobs with a tile plan advance together, one launch per MCS
+        # for all of them; any others run alone on the remaining streams
+        tiled = [w for w in large if w[1].L % 8 == 0 and w[1].L >= 16]
+        alone = [w for w in large if not (w[1].L % 8 == 0 and w[1].L >= 16)]
+        if tiled:
+            with torch.cuda.stream(self.streams[0]):
+                escg.step_batch([h["p"] for h, _, _, _ in tiled],
+                                [h["lat"] for h, _, _, _ in tiled],
+                                [m0 for _, _, m0, _ in tiled],
+                                [n for _, _, _, n in tiled])
+                ev = torch.cuda.Event()
+                ev.record()
+                done.append(ev)
+        others = self.streams[1:] or self.streams
+        for i, (h, r, m0, n) in enumerate(alone):
+            s = others[i % len(others)]
             with torch.cuda.stream(s):
                 escg.step_mcs(h["p"], h["lat"], m0, n, None)
                 ev = torch.cuda.Event()

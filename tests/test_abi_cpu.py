@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from paper_2508_16639_amd import escg
+from paper_2508_16639_amd import escg, workloads
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -58,6 +58,21 @@ def test_thresholds_match_oracle(rates):
     p = escg.Params(L=8, S=3, dom=escg.circulant_dom(3, [1]), ex=rates[0],
                     sel=rates[1], rep=rates[2])
     assert escg.thresholds(p) == O.thresholds(*rates)
+
+
+@pytest.mark.parametrize("M,L,eps", [(1e-5, 3200, 51.2), (1e-4, 512, 13.1072),
+                                     (1e-3, 64, 2.048), (0.0, 100, 0.0)])
+def test_eps_from_mobility_is_the_workload_convention(M, L, eps):
+    # M = 2 eps / N with N = L^2 sites; the workload tables quote these eps
+    assert escg.eps_from_mobility(M, L) == pytest.approx(eps, rel=1e-12)
+    assert escg.eps_from_mobility(M, L) == workloads.eps_from_mobility(M, L)
+
+
+@pytest.mark.parametrize("M,L", [(-1e-5, 64), (float("nan"), 64),
+                                 (float("inf"), 64), (1e-5, 0)])
+def test_eps_from_mobility_rejects_bad_input(M, L):
+    with pytest.raises(escg.EscgError):
+        escg.eps_from_mobility(M, L)
 
 
 def _bad_params():

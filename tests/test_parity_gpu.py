@@ -154,6 +154,37 @@ def test_imported_dominance_bit_exact(name, D, L, route):
     assert np.array_equal(c, rc)
 
 
+def test_step_batch_matches_oracle_per_job():
+    # jobs of both kernel instantiations (S <= 7 and S > 7), different sides,
+    # chunk lengths (0, odd and even: the state ends in the lattice or in
+    # the scratch buffer) and start MCS
+    specs = [(16, 3, [1], 3, 0), (64, 5, [1, 3], 0, 5), (136, 8, [1, 2, 5], 2, 9),
+             (64, 13, [1, 2, 5], 1, 2), (200, 3, [1], 4, 100), (24, 2, [1], 5, 1),
+             (800, 5, [1, 3], 2, 7)]
+    ps, js, lats, g0s = [], [], [], []
+    for i, (L, S, K, n, m0) in enumerate(specs):
+        p, j = pair(L, S, K, 0.7 + i, 1.0, 1.0, seed=50 + i, replica=i)
+        g0 = random_lattice(L, S, seed=L + i, domain=2)
+        ps.append(p)
+        js.append(j)
+        g0s.append(g0)
+        lats.append(dev(g0))
+    escg.step_batch(ps, lats, [s[4] for s in specs], [s[3] for s in specs])
+    for (L, S, K, n, m0), j, g0, lat in zip(specs, js, g0s, lats):
+        ref = g0.copy()
+        O.o2_run(j, ref, m0, n)
+        assert np.array_equal(host(lat), ref), (L, S, n)
+
+
+def test_step_batch_rejects_lattices_without_tile_plan():
+    p, _ = pair(100, 3, [1], 1.0)
+    g0 = random_lattice(100, 3, seed=3)
+    lat = dev(g0)
+    with pytest.raises(escg.EscgError):
+        escg.step_batch([p], [lat], [0], [2])
+    assert np.array_equal(host(lat), g0)   # nothing was enqueued
+
+
 @pytest.mark.parametrize("route", ["lds", "tiled", "persistent"])
 def test_zero_mcs_writes_only_row0(route):
     route_to(route)
