@@ -203,18 +203,21 @@ escg_status escg_step_batch(uint32_t n, const escg_params *h_params,
                             uint8_t *const *h_lattices, const uint32_t *h_mcs0,
                             const uint32_t *h_n_mcs, void *stream);
 
-/* Single-job routing knob: escg_step_mcs keeps a lattice with
- * L <= min(L_max, escg_batch_max_L()) whole in one workgroup's LDS and sends
- * larger ones to the tiled all-CU path (default 192).  Both paths produce
- * the same bytes; the knob only trades latency for occupancy.  Process-wide;
- * always ESCG_OK. */
+/* Single-job routing (escg_step_mcs, escg_run_until_extinction), in order:
+ *   1. L % 8 == 0 and L >= persistent_min_L: one persistent cooperative
+ *      launch keeps every tile in LDS for all MCS (run-until: chunks of such
+ *      launches with an exact stop);
+ *   2. L <= min(single_lds_max_L, escg_batch_max_L(S)): the whole lattice in
+ *      one workgroup's LDS;
+ *   3. otherwise one tiled launch per MCS.
+ * Defaults: persistent_min_L = 72, single_lds_max_L = 0xFFFFFFFF (as large
+ * as fits).  Every path produces the same bytes; the knobs only trade
+ * latency for occupancy.  Process-wide; the setters always return
+ * ESCG_OK, the getters return the current values. */
 escg_status escg_set_single_lds_max_L(uint32_t L_max);
-
-/* Routing knob: escg_step_mcs runs lattices with L >= L_min (and L % 8 == 0)
- * in one persistent cooperative launch that keeps every tile in LDS for all
- * MCS (default 400); smaller or unsupported lattices use one launch per
- * MCS.  Same bytes either way.  Process-wide; always ESCG_OK. */
 escg_status escg_set_persistent_min_L(uint32_t L_min);
+uint32_t escg_single_lds_max_L(void);
+uint32_t escg_persistent_min_L(void);
 
 /* Which kernel path the calling thread's last escg_step_mcs with n_mcs > 0
  * enqueued: the whole lattice in one workgroup's LDS, one tiled launch per

@@ -79,6 +79,7 @@ def tune(torch, escg, L: int, S: int, K=None, ex: float = 1.0,
     lat = torch.empty(L * L, dtype=torch.uint8, device="cuda")
     cnt = torch.empty((n_mcs + 1) * (S + 1), dtype=torch.int32, device="cuda")
     escg.init(p, lat)
+    old_min = escg.persistent_min_L()
     escg.set_persistent_min_L(0)
     results = []
     try:
@@ -101,7 +102,7 @@ def tune(torch, escg, L: int, S: int, K=None, ex: float = 1.0,
                             "us_per_mcs": best / n_mcs * 1e6})
     finally:
         escg.set_tile_shape(L, 0, 0)
-        escg.set_persistent_min_L(400)
+        escg.set_persistent_min_L(old_min)
     escg.async_status()
     if not results:
         return {}

@@ -55,7 +55,7 @@ struct JobDev {
     uint32_t dom[32];
 };
 
-__device__ __forceinline__ bool stop_met(const uint32_t *c, uint32_t S,
+__host__ __device__ inline bool stop_met(const uint32_t *c, uint32_t S,
                                          uint32_t mode)
 {
     if (mode == ESCG_STOP_NONE)
@@ -809,7 +809,7 @@ uint32_t lds_max_L(uint32_t S)
 
 // Single jobs run in the LDS-resident kernel up to this L (one workgroup, so
 // larger single lattices go to the tiled multi-workgroup path).
-std::atomic<uint32_t> g_single_lds_max_L{192};
+std::atomic<uint32_t> g_single_lds_max_L{0xFFFFFFFFu};
 
 thread_local char g_last_error[160] = "";
 thread_local uint32_t g_last_route = 0;
@@ -960,7 +960,7 @@ uint32_t tiled_threads(const TileGeom &G, uint32_t cap)
     return nt;
 }
 
-std::atomic<uint32_t> g_tiled_min_L{400};
+std::atomic<uint32_t> g_tiled_min_L{72};
 
 // Tile-shape overrides per lattice side (autotuner results), both tiled
 // paths.  Guarded by g_shape_mu.
@@ -1213,6 +1213,111 @@ escg_status run_tiled_persistent(const escg_params *p, const Derived &d,
     return s;
 }
 
+// Run-until on the persistent kernel: chunks of MCS with per-MCS counts;
+// after each chunk the host reads the counts and finds the first MCS that
+// meets the stop condition; if it lies inside the chunk, the chunk is re-run
+// from its saved start up to that MCS, so the lattice is left exactly at the
+// stopping state.  ESCG_EUNSUPPORTED (nothing but a lattice copy enqueued)
+// if the persistent launch is refused on the first chunk.
+escg_status run_until_persistent(const escg_params *p, const Derived &d,
+                                 uint8_t *lattice, uint32_t mcs0,
+                                 uint32_t max_mcs, uint32_t mode,
+                                 uint32_t *d_result, hipStream_t st)
+{
+    const uint32_t L = p->L, S = p->S, N = L * L, W = S + 1;
+    const uint32_t chunk_max = 1024;
+    const size_t cnt_bytes = (size_t)(chunk_max + 1) * W * 4;
+    const size_t lat_off = (cnt_bytes + 255) & ~(size_t)255;
+    uint8_t *scr = nullptr;
+    if (hipMallocAsync((void **)&scr, lat_off + N, st) != hipSuccess)
+        return ESCG_ENOMEM;
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(scr);
+    uint8_t *saved = scr + lat_off;
+    std::vector<uint32_t> h((size_t)(chunk_max + 1) * W);
+    std::vector<uint32_t> res(S + 3, 0);
+    escg_status s = ESCG_OK;
+    auto finish = [&](uint32_t flag, uint32_t t, const uint32_t *row) {
+        res[0] = flag;
+        res[1] = t;
+        for (uint32_t v = 0; v < W; ++v)
+            res[2 + v] = row[v];
+        if (hipMemcpyAsync(d_result, res.data(), res.size() * 4,
+                           hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            s = ESCG_EDEVICE;
+    };
+    // the sticky abort word of the persistent kernel is read with the
+    // counts; a change from 0 during this call means a chunk was aborted
+    uint32_t aerr = 0, aerr0 = 0;
+    auto fetch = [&](uint32_t rows) {
+        return hipMemcpyAsync(h.data(), cnt, (size_t)rows * W * 4,
+                              hipMemcpyDeviceToHost, st) == hipSuccess &&
+               hipMemcpyFromSymbolAsync(&aerr, HIP_SYMBOL(g_async_error),
+                                        sizeof(aerr), 0,
+                                        hipMemcpyDeviceToHost,
+                                        st) == hipSuccess &&
+               hipStreamSynchronize(st) == hipSuccess;
+    };
+    // the input state
+    launch_fill(cnt, W, 0, st);
+    s = launch_densities(lattice, N, S, cnt, st);
+    if (s == ESCG_OK && !fetch(1))
+        s = ESCG_EDEVICE;
+    aerr0 = aerr;
+    if (s == ESCG_OK && (mode != ESCG_STOP_NONE && stop_met(h.data(), S, mode))) {
+        finish(1, 0, h.data());
+        (void)hipFreeAsync(scr, st);
+        return s;
+    }
+    uint32_t t = 0, chunk = 64;
+    std::vector<uint32_t> last(h.begin(), h.begin() + W);
+    while (s == ESCG_OK && t < max_mcs) {
+        const uint32_t n = std::min(chunk, max_mcs - t);
+        launch_copy(saved, lattice, N, st);
+        s = run_tiled_persistent(p, d, lattice, mcs0 + t, n, cnt, st);
+        if (s != ESCG_OK)
+            break; // EUNSUPPORTED on the first chunk: the caller falls back
+        if (!fetch(n + 1)) {
+            s = ESCG_EDEVICE;
+            break;
+        }
+        if (aerr && !aerr0) {
+            std::snprintf(g_last_error, sizeof(g_last_error),
+                          "persistent kernel aborted (neighbour wait timed "
+                          "out) in MCS %u..%u", mcs0 + t, mcs0 + t + n - 1);
+            s = ESCG_ETIMEOUT;
+            break;
+        }
+        uint32_t hit = 0;
+        for (uint32_t k = 1; k <= n && mode != ESCG_STOP_NONE; ++k)
+            if (stop_met(h.data() + (size_t)k * W, S, mode)) {
+                hit = k;
+                break;
+            }
+        if (hit) {
+            if (hit < n) {
+                launch_copy(lattice, saved, N, st);
+                s = run_tiled_persistent(p, d, lattice, mcs0 + t, hit,
+                                         nullptr, st);
+                if (s != ESCG_OK)
+                    break;
+            }
+            finish(1, t + hit, h.data() + (size_t)hit * W);
+            break;
+        }
+        std::copy(h.begin() + (size_t)n * W, h.begin() + (size_t)(n + 1) * W,
+                  last.begin());
+        t += n;
+        chunk = std::min(chunk_max, chunk * 2);
+        if (t == max_mcs)
+            finish(0, max_mcs, last.data());
+    }
+    if (s == ESCG_OK && max_mcs == 0)
+        finish(0, 0, last.data());
+    (void)hipFreeAsync(scr, st);
+    return s;
+}
+
 bool aligned4(const void *p) { return ((uintptr_t)p & 3u) == 0; }
 
 } // namespace
@@ -1330,7 +1435,8 @@ escg_status escg_step_mcs(const escg_params *p, uint8_t *d_lattice,
     hipStream_t st = S_(stream);
     const Derived d = derive(p);
     const uint32_t L = p->L, S = p->S, N = L * L;
-    if (L <= std::min(g_single_lds_max_L.load(), lds_max_L(S))) {
+    const bool persistent = (L & 7u) == 0 && L >= g_tiled_min_L.load();
+    if (!persistent && L <= std::min(g_single_lds_max_L.load(), lds_max_L(S))) {
         JobDev J = make_job(p, d, 0, mcs0, n_mcs, ESCG_STOP_NONE, 0, d_counts,
                             nullptr, 0);
         g_last_route = ESCG_ROUTE_LDS;
@@ -1344,13 +1450,20 @@ escg_status escg_step_mcs(const escg_params *p, uint8_t *d_lattice,
     }
     if (n_mcs == 0)
         return ESCG_OK;
-    if (L >= g_tiled_min_L.load()) {
+    if (persistent) {
         s = run_tiled_persistent(p, d, d_lattice, mcs0, n_mcs, d_counts, st);
         if (s != ESCG_EUNSUPPORTED) {
             g_last_route = ESCG_ROUTE_PERSISTENT;
             return s;
         }
         s = ESCG_OK;
+        if (L <= std::min(g_single_lds_max_L.load(), lds_max_L(S))) {
+            // counts row 0 is already written; the LDS path rewrites it
+            JobDev J = make_job(p, d, 0, mcs0, n_mcs, ESCG_STOP_NONE, 0,
+                                d_counts, nullptr, 0);
+            g_last_route = ESCG_ROUTE_LDS;
+            return launch_lds_single(J, d.small, d_lattice, st);
+        }
     }
     g_last_route = ESCG_ROUTE_TILED;
     uint8_t *other = nullptr;
@@ -1402,11 +1515,22 @@ escg_status escg_run_until_extinction(const escg_params *p, uint8_t *d_lattice,
     hipStream_t st = S_(stream);
     const Derived d = derive(p);
     const uint32_t L = p->L, S = p->S, N = L * L;
-    if (L <= lds_max_L(S)) {
+    if ((L & 7u) == 0 && L >= g_tiled_min_L.load()) {
+        s = run_until_persistent(p, d, d_lattice, mcs0, max_mcs, mode,
+                                 d_result, st);
+        if (s != ESCG_EUNSUPPORTED) {
+            g_last_route = ESCG_ROUTE_PERSISTENT;
+            return s;
+        }
+        s = ESCG_OK;
+    }
+    if (L <= std::min(g_single_lds_max_L.load(), lds_max_L(S))) {
         JobDev J = make_job(p, d, 0, mcs0, max_mcs, mode, 0, nullptr,
                             d_result, S + 3);
+        g_last_route = ESCG_ROUTE_LDS;
         return launch_lds_single(J, d.small, d_lattice, st);
     }
+    g_last_route = ESCG_ROUTE_TILED;
     // Large lattice: tile MCS launches with a device stop flag, polled by
     // the host every chunk.
     uint8_t *scratch = nullptr;
@@ -1516,6 +1640,10 @@ escg_status escg_set_persistent_min_L(uint32_t L)
     g_tiled_min_L = L;
     return ESCG_OK;
 }
+
+uint32_t escg_single_lds_max_L(void) { return g_single_lds_max_L.load(); }
+
+uint32_t escg_persistent_min_L(void) { return g_tiled_min_L.load(); }
 
 escg_status escg_async_status(int reset)
 {

@@ -8,6 +8,7 @@ There is no CPU fallback: if ``libescg.so`` is missing or fails to load,
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 from dataclasses import dataclass
@@ -48,6 +49,7 @@ EXPORTS = ("escg_status_str", "escg_last_error", "escg_circulant_dom", "escg_dom
            "escg_run_until_extinction", "escg_batch_max_L", "escg_batch_run",
            "escg_step_batch",
            "escg_set_single_lds_max_L", "escg_set_persistent_min_L",
+           "escg_single_lds_max_L", "escg_persistent_min_L",
            "escg_async_status", "escg_last_route", "escg_set_tile_shape",
            "escg_tile_plan")
 
@@ -92,6 +94,10 @@ def lib():
     L.escg_step_batch.argtypes = [u32, P, C.POINTER(C.c_void_p), u32p,
                                   u32p, vp]
     L.escg_set_single_lds_max_L.argtypes = [u32]
+    L.escg_single_lds_max_L.argtypes = []
+    L.escg_single_lds_max_L.restype = u32
+    L.escg_persistent_min_L.argtypes = []
+    L.escg_persistent_min_L.restype = u32
     L.escg_set_persistent_min_L.argtypes = [u32]
     L.escg_async_status.argtypes = [C.c_int]
     L.escg_set_tile_shape.argtypes = [u32, u32, u32]
@@ -100,7 +106,8 @@ def lib():
     L.escg_last_route.restype = u32
     for name in EXPORTS:
         if name not in ("escg_status_str", "escg_batch_max_L",
-                        "escg_last_error", "escg_last_route"):
+                        "escg_last_error", "escg_last_route",
+                        "escg_single_lds_max_L", "escg_persistent_min_L"):
             getattr(L, name).restype = C.c_int32
     _lib = L
     return L
@@ -183,6 +190,31 @@ def eps_from_mobility(M: float, L: int) -> float:
 
 def batch_max_L(S: int = 3) -> int:
     return int(lib().escg_batch_max_L(int(S)))
+
+
+def persistent_min_L() -> int:
+    return int(lib().escg_persistent_min_L())
+
+
+def single_lds_max_L() -> int:
+    return int(lib().escg_single_lds_max_L())
+
+
+@contextlib.contextmanager
+def routing(single_lds_max: Optional[int] = None,
+            persistent_min: Optional[int] = None):
+    """Sets the single-job routing knobs inside the block and restores the
+    previous values afterwards."""
+    old = (single_lds_max_L(), persistent_min_L())
+    try:
+        if single_lds_max is not None:
+            set_single_lds_max_L(single_lds_max)
+        if persistent_min is not None:
+            set_persistent_min_L(persistent_min)
+        yield
+    finally:
+        set_single_lds_max_L(old[0])
+        set_persistent_min_L(old[1])
 
 
 def set_persistent_min_L(L: int) -> None:

@@ -256,13 +256,16 @@ class DeviceExecutor:
                 ev.record()
                 done.append(ev)
         others = self.streams[1:] or self.streams
-        for i, (h, r, m0, n) in enumerate(alone):
-            s = others[i % len(others)]
-            with torch.cuda.stream(s):
-                escg.step_mcs(h["p"], h["lat"], m0, n, None)
-                ev = torch.cuda.Event()
-                ev.record()
-                done.append(ev)
+        # one launch per MCS for these too: a cooperative persistent launch
+        # would wait for CUs that the batched launches hold
+        with escg.routing(persistent_min=1 << 30):
+            for i, (h, r, m0, n) in enumerate(alone):
+                s = others[i % len(others)]
+                with torch.cuda.stream(s):
+                    escg.step_mcs(h["p"], h["lat"], m0, n, None)
+                    ev = torch.cuda.Event()
+                    ev.record()
+                    done.append(ev)
         for ev in done:
             cur.wait_event(ev)
         cur.synchronize()
@@ -331,12 +334,7 @@ def bench_serving(torch, escg, workloads, n_jobs: int = 2000):
     one-at-a-time serving, on the same GPU."""
     reqs = workloads.serving_requests(n=n_jobs)
     ex = DeviceExecutor(torch, escg)
-    # large jobs share the GPU with the batch: per-MCS tiled launches
-    escg.set_persistent_min_L(1 << 30)
-    try:
-        st, _ = Scheduler(ex).run(reqs)
-    finally:
-        escg.set_persistent_min_L(400)
+    st, _ = Scheduler(ex).run(reqs)
     escg.async_status()
     plain = plain_serving(torch, escg, reqs)
     s = st.summary()

@@ -137,7 +137,12 @@ def test_batch_rejects_overlap_and_bad_jobs():
 
 
 def test_routing_knobs_and_limits_callable_without_gpu():
-    escg.set_single_lds_max_L(192)
-    escg.set_persistent_min_L(400)
+    # defaults: persistent kernel from L = 72 (L % 8 == 0), LDS otherwise
+    assert escg.persistent_min_L() == 72
+    assert escg.single_lds_max_L() == 0xFFFFFFFF
+    with escg.routing(single_lds_max=192, persistent_min=400):
+        assert (escg.single_lds_max_L(), escg.persistent_min_L()) == (192, 400)
+    assert (escg.single_lds_max_L(), escg.persistent_min_L()) == \
+        (0xFFFFFFFF, 72)
     assert escg.batch_max_L(0) == 0 and escg.batch_max_L(32) == 0
     assert escg.batch_max_L(3) >= escg.batch_max_L(31) > 0

@@ -1,0 +1,77 @@
+"""Host side of the command-line driver: the CSV formats round-trip, and
+options the build does not support are refused before any device work."""
+import numpy as np
+import pytest
+
+from paper_2508_16639_amd import cli, escg, escg_io
+
+
+def test_dominance_csv_round_trip_and_bitmasks(tmp_path):
+    # RPSLS with one edge of the five-species cycle removed (the ablated
+    # network the paper imports to replicate Zhong et al.)
+    D = np.array([[0, 1, 0, 1, 0], [0, 0, 1, 0, 1], [1, 0, 0, 1, 0],
+                  [0, 1, 0, 0, 1], [1, 0, 1, 0, 0]], np.uint8)
+    D[0, 1] = 0
+    f = tmp_path / "dominance.csv"
+    escg_io.write_dominance_csv(str(f), D)
+    back = escg_io.read_dominance_csv(str(f))
+    assert np.array_equal(back, D)
+    dom = escg.dom_from_matrix(back)
+    for a in range(1, 6):
+        for b in range(1, 6):
+            assert ((dom[a] >> b) & 1) == D[a - 1, b - 1]
+
+
+@pytest.mark.parametrize("text", ["0,1\n1\n", "0,2\n1,0\n", ""])
+def test_dominance_csv_rejects_bad_matrices(tmp_path, text):
+    f = tmp_path / "d.csv"
+    f.write_text(text)
+    with pytest.raises(ValueError):
+        escg_io.read_dominance_csv(str(f))
+
+
+def test_grid_csv_round_trip(tmp_path):
+    rng = np.random.default_rng(5)
+    g = rng.integers(0, 6, size=17 * 17, dtype=np.uint8)
+    f = tmp_path / "grid.csv"
+    escg_io.write_grid_csv(str(f), g, 17, 1234)
+    back, L, mcs = escg_io.read_grid_csv(str(f))
+    assert L == 17 and mcs == 1234 and np.array_equal(back, g)
+    lines = f.read_text().splitlines()
+    assert len(lines) == 18 and lines[-1] == "1234"
+
+
+def test_densities_csv_rows(tmp_path):
+    f = tmp_path / "densities.csv"
+    c = np.array([[10, 20, 70], [12, 18, 70]], np.uint32)
+    escg_io.append_densities_csv(str(f), c, 5, 100)
+    escg_io.append_densities_csv(str(f), c[:1], 7, 100)
+    mcs, d = escg_io.read_densities_csv(str(f))
+    assert list(mcs) == [5, 6, 7]
+    assert np.allclose(d, np.array([[.1, .2, .7], [.12, .18, .7], [.1, .2, .7]]))
+    assert f.read_text().splitlines()[0] == "mcs,empty,species_1,species_2"
+
+
+def test_params_csv_round_trip(tmp_path):
+    f = tmp_path / "params.csv"
+    escg_io.write_params_csv(str(f), {"length": 64, "mobility": repr(3e-5)})
+    assert escg_io.read_params_csv(str(f)) == {"length": "64",
+                                               "mobility": "3e-05"}
+
+
+@pytest.mark.parametrize("argv", [["--height", "100"], ["--neighbourhood", "8"],
+                                  ["--flux", "false"]])
+def test_unsupported_options_refused_before_device_work(argv):
+    args = cli.build_parser().parse_args(["--length", "64"] + argv)
+    with pytest.raises(SystemExit):
+        cli.Run(args, None, escg)
+
+
+def test_paper_flags_parse_with_defaults():
+    a = cli.build_parser().parse_args([])
+    assert (a.length, a.mcs, a.neighbourhood, a.printFrequency, a.species,
+            a.flux) == (200, 100000, 4, 200, 3, True)
+    assert a.mobility == 3e-5
+    a = cli.build_parser().parse_args(["--maxStep", "true", "--numRandoms",
+                                       "1000", "--dominance", "true"])
+    assert a.maxStep is True and a.dominance == "true"

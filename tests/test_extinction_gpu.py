@@ -55,6 +55,46 @@ def test_run_until_input_already_met():
     assert np.array_equal(host(lat), g)
 
 
+# species 1 beats 2 and 3, which do not interact: 1 takes over, at times
+# (weak selection) that fall in the second to fifth chunk of the persistent
+# runner (chunks of 64, 128, 256, 512, 1024 MCS)
+D_TAKEOVER = np.array([[0, 1, 1], [0, 0, 0], [0, 0, 0]], np.uint8)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("L,ex,sel,cap", [(80, 0.5, 1.0, 200),
+                                          (80, 0.5, 0.03, 3000),
+                                          (96, 1.0, 0.01, 3000)])
+def test_run_until_persistent_chunks_stop_exactly(mode, L, ex, sel, cap):
+    cap = cap if mode != escg.STOP_NONE else 150
+    for rep in range(2):
+        p, j = pair(L, 3, None, ex, sel, 1.0, seed=77, replica=rep,
+                    D=D_TAKEOVER)
+        g0 = j.init()
+        lat = dev(g0)
+        res = torch.full((6,), -1, dtype=torch.int32, device="cuda:0")
+        escg.run_until_extinction(p, lat, 5, cap, mode, res)
+        assert escg.last_route() == "persistent", escg.last_error()
+        ref = g0.copy()
+        r = oracle_until(j, ref, 5, cap, mode)
+        assert np.array_equal(host(res), r), (rep, host(res), r)
+        assert np.array_equal(host(lat), ref)
+        if mode != escg.STOP_NONE:
+            assert r[0] == 1
+
+
+def test_run_until_persistent_input_already_met():
+    p, j = pair(96, 3, [1], 1.0)
+    g = np.zeros(96 * 96, np.uint8)
+    g[:10] = 2
+    res = torch.full((6,), -1, dtype=torch.int32, device="cuda:0")
+    lat = dev(g)
+    escg.run_until_extinction(p, lat, 0, 100, escg.STOP_FIRST_EXTINCTION, res)
+    assert escg.last_route() == "persistent"
+    assert host(res).tolist() == [1, 0, 96 * 96 - 10, 0, 10, 0]
+    assert np.array_equal(host(lat), g)
+
+
 def _batch(jobs, mode, init, mcs0=None):
     """jobs: list of (Params, oracle Job, cap, g0 or None)."""
     offs, off = [], 0

@@ -15,6 +15,9 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
+DEFAULT_ROUTING = (escg.single_lds_max_L(), escg.persistent_min_L())
+
+
 def route_to(route):
     """Force one of the three MCS paths (all must give the same bytes)."""
     if route == "lds":
@@ -27,8 +30,8 @@ def route_to(route):
         escg.set_single_lds_max_L(0)
         escg.set_persistent_min_L(0)
     else:
-        escg.set_single_lds_max_L(192)
-        escg.set_persistent_min_L(400)
+        escg.set_single_lds_max_L(DEFAULT_ROUTING[0])
+        escg.set_persistent_min_L(DEFAULT_ROUTING[1])
 
 
 @pytest.fixture(autouse=True)

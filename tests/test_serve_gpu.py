@@ -41,12 +41,8 @@ def alone_gpu(r):
 def test_server_results_equal_alone_runs():
     reqs = requests()
     ex = DeviceExecutor(torch, escg, keep_lattices=True)
-    escg.set_persistent_min_L(1 << 30)
-    try:
-        st, jobs = Scheduler(ex, ServerConfig(work_per_iter=2e6,
-                                              min_chunk=3)).run(reqs)
-    finally:
-        escg.set_persistent_min_L(400)
+    st, jobs = Scheduler(ex, ServerConfig(work_per_iter=2e6,
+                                          min_chunk=3)).run(reqs)
     escg.async_status()
     assert st.completed == len(reqs) and st.failed == 0
     assert st.iterations > 1 and st.peak_active > 1
@@ -67,10 +63,6 @@ def test_server_under_small_hbm_budget_queues_instead_of_dropping():
     ex = DeviceExecutor(torch, escg)
     cfg = ServerConfig(hbm_budget=2 * 2 * 800 * 800 + 3 * 4096,
                        work_per_iter=2e6, min_chunk=3)
-    escg.set_persistent_min_L(1 << 30)
-    try:
-        st, jobs = Scheduler(ex, cfg).run(reqs)
-    finally:
-        escg.set_persistent_min_L(400)
+    st, jobs = Scheduler(ex, cfg).run(reqs)
     assert st.completed == len(reqs) and st.failed == 0
     assert st.peak_footprint <= cfg.hbm_budget
