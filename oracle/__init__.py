@@ -56,7 +56,8 @@ def lib():
         u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
         u32 = C.c_uint32
         dbl = C.c_double
-        job = [u32, u32, u8p, dbl, dbl, dbl, C.c_uint64, u32, C.c_int]
+        job = [u32, u32, u8p, dbl, dbl, dbl, C.c_uint64, u32, C.c_int,
+               C.c_int]
         L.orc_philox4x32.argtypes = [u32p, u32p, C.c_int, u32p]
         L.orc_circulant_matrix.argtypes = [u32, u32, u8p]
         L.orc_pair_rule.argtypes = [C.c_int, C.c_uint8, C.c_uint8, u32, u8p,
@@ -136,7 +137,9 @@ def counts(grid: np.ndarray, L: int, S: int) -> np.ndarray:
 class Job:
     """One simulation: lattice side L (even for O2), S species with flat
     dominance matrix D (S x S, paper layout), rates by role (exchange =
-    migration, selection = interaction, reproduction), and the RNG key."""
+    migration, selection = interaction, reproduction), the RNG key, and the
+    neighbourhood (4-way von Neumann or 8-way Moore, the paper's
+    --neighbourhood option)."""
     L: int
     S: int
     D: np.ndarray
@@ -146,17 +149,19 @@ class Job:
     seed: int = 1
     replica: int = 0
     rounds: int = 10
+    nbhd: int = 4          # 4: von Neumann, 8: Moore
     _Dflat: np.ndarray = field(init=False, repr=False)
 
     def __post_init__(self):
         D = np.ascontiguousarray(self.D, dtype=np.uint8).reshape(-1)
         assert D.size == self.S * self.S
+        assert self.nbhd in (4, 8)
         self._Dflat = D
 
     def args(self):
         return (self.L, self.S, self._Dflat, float(self.ex), float(self.sel),
                 float(self.rep), int(self.seed), int(self.replica),
-                int(self.rounds))
+                int(self.rounds), int(self.nbhd))
 
     def init(self) -> np.ndarray:
         return init_lattice(self.L, self.S, self.seed, self.replica,

@@ -222,9 +222,18 @@ void orc_counts(uint32_t L, uint32_t S, const uint8_t *grid, uint32_t *counts)
 /* Philox(ctr = (by*Q + (bx>>2), t, (TAG_PASS<<8) | p, replica)) with        */
 /* Q = ceil((L/2)/4), so one Philox call serves four horizontally adjacent   */
 /* blocks of one block row.  From w:                                         */
+/*   von Neumann neighbourhood (nbhd = 4):                                   */
 /*   bits 0-1  edge:        0 -> (A,B)  1 -> (C,D)  2 -> (A,C)  3 -> (B,D)   */
 /*   bit  2    orientation: 0 -> the first site of the edge is the selected  */
 /*                          cell, 1 -> the second one is                     */
+/*   Moore neighbourhood (nbhd = 8):                                         */
+/*   bits 0-2  pair: 0 -> (A,B)  1 -> (C,D)  2 -> (A,C)  3 -> (B,D)          */
+/*                   4 -> (A,D)  5 -> (B,C)  6 -> (A,D)  7 -> (B,C)          */
+/*             (a diagonal lies inside a block for one offset in four, an    */
+/*             axis edge for one in two, so the diagonals take two slots:    */
+/*             every one of the 4N Moore pairs is then updated with the same */
+/*             probability 1/16 per pass, as under random-sequential steps)  */
+/*   bit  3    orientation, as bit 2 above                                   */
 /*   bits 8-31 u24, the action by the thresholds above                       */
 /* and the pair rule is applied to (selected cell, neighbour).  Blocks are   */
 /* disjoint, so the order in which blocks are visited is irrelevant.         */
@@ -236,6 +245,7 @@ typedef struct {
     uint64_t seed;
     uint32_t replica;
     int rounds;
+    int nbhd; /* 4 (von Neumann) or 8 (Moore) */
 } o2_job;
 
 static void o2_pass(const o2_job *j, uint32_t t, uint32_t p, uint8_t *grid)
@@ -254,14 +264,18 @@ static void o2_pass(const o2_job *j, uint32_t t, uint32_t p, uint8_t *grid)
             uint64_t A = (uint64_t)r0 * L + c0, B = (uint64_t)r0 * L + c1;
             uint64_t C = (uint64_t)r1 * L + c0, Dd = (uint64_t)r1 * L + c1;
             uint64_t first, second;
-            switch (w & 3u) {
+            uint32_t pair = j->nbhd == 8 ? (w & 7u) : (w & 3u);
+            uint32_t orient = j->nbhd == 8 ? (w >> 3) & 1u : (w >> 2) & 1u;
+            switch (pair) {
             case 0: first = A; second = B; break;
             case 1: first = C; second = Dd; break;
             case 2: first = A; second = C; break;
-            default: first = B; second = Dd; break;
+            case 3: first = B; second = Dd; break;
+            case 4: case 6: first = A; second = Dd; break;
+            default: first = B; second = C; break;
             }
             uint64_t cell = first, nbr = second;
-            if ((w >> 2) & 1u) {
+            if (orient) {
                 cell = second;
                 nbr = first;
             }
@@ -279,11 +293,11 @@ static void o2_mcs(const o2_job *j, uint32_t t, uint8_t *grid)
 
 static o2_job make_job(uint32_t L, uint32_t S, const uint8_t *D, double ex,
                        double sel, double rep, uint64_t seed, uint32_t replica,
-                       int rounds)
+                       int rounds, int nbhd)
 {
     o2_job j;
     j.L = L; j.S = S; j.D = D; j.seed = seed; j.replica = replica;
-    j.rounds = rounds;
+    j.rounds = rounds; j.nbhd = nbhd;
     orc_thresholds(ex, sel, rep, &j.T1, &j.T2);
     return j;
 }
@@ -291,9 +305,10 @@ static o2_job make_job(uint32_t L, uint32_t S, const uint8_t *D, double ex,
 /* One pass only, for the one-pass distribution tests. */
 void orc_o2_pass(uint32_t L, uint32_t S, const uint8_t *D, double ex,
                  double sel, double rep, uint64_t seed, uint32_t replica,
-                 int rounds, uint32_t t, uint32_t p, uint8_t *grid)
+                 int rounds, int nbhd, uint32_t t, uint32_t p,
+                 uint8_t *grid)
 {
-    o2_job j = make_job(L, S, D, ex, sel, rep, seed, replica, rounds);
+    o2_job j = make_job(L, S, D, ex, sel, rep, seed, replica, rounds, nbhd);
     o2_pass(&j, t, p, grid);
 }
 
@@ -303,10 +318,10 @@ void orc_o2_pass(uint32_t L, uint32_t S, const uint8_t *D, double ex,
  * each MCS and once more at the end. */
 void orc_o2_run(uint32_t L, uint32_t S, const uint8_t *D, double ex,
                 double sel, double rep, uint64_t seed, uint32_t replica,
-                int rounds, uint32_t mcs0, uint32_t n_mcs, uint8_t *grid,
-                uint32_t *counts)
+                int rounds, int nbhd, uint32_t mcs0, uint32_t n_mcs,
+                uint8_t *grid, uint32_t *counts)
 {
-    o2_job j = make_job(L, S, D, ex, sel, rep, seed, replica, rounds);
+    o2_job j = make_job(L, S, D, ex, sel, rep, seed, replica, rounds, nbhd);
     if (counts)
         orc_counts(L, S, grid, counts);
     for (uint32_t k = 0; k < n_mcs; ++k) {
@@ -339,10 +354,10 @@ static int stop_met(uint32_t S, const uint32_t *c, int mode)
  * t_ext. */
 void orc_o2_run_until(uint32_t L, uint32_t S, const uint8_t *D, double ex,
                       double sel, double rep, uint64_t seed, uint32_t replica,
-                      int rounds, uint32_t mcs0, uint32_t max_mcs, int mode,
-                      uint8_t *grid, uint32_t *result)
+                      int rounds, int nbhd, uint32_t mcs0, uint32_t max_mcs,
+                      int mode, uint8_t *grid, uint32_t *result)
 {
-    o2_job j = make_job(L, S, D, ex, sel, rep, seed, replica, rounds);
+    o2_job j = make_job(L, S, D, ex, sel, rep, seed, replica, rounds, nbhd);
     uint32_t *c = result + 2;
     uint32_t t = 0;
     orc_counts(L, S, grid, c);
@@ -361,14 +376,16 @@ void orc_o2_run_until(uint32_t L, uint32_t S, const uint8_t *D, double ex,
 /* O1: random-sequential update, Algorithm "Elementary Step" N times per     */
 /* MCS.  Its own random stream: elementary step number k (64-bit, counted    */
 /* from 0 at mcs0 * N) uses Philox(ctr = (lo(k), hi(k), TAG_RSU<<8,          */
-/* replica)): word 0 picks the cell, floor(w0 * N / 2^32); word 1 bits 0-1   */
-/* pick the direction (up, down, left, right); words 2 and 3 give a double  */
+/* replica)): word 0 picks the cell, floor(w0 * N / 2^32); word 1 picks the */
+/* neighbour: bits 0-1 (up, down, left, right) for the von Neumann          */
+/* neighbourhood, bits 0-2 (those four, then up-left, up-right, down-left,   */
+/* down-right) for the Moore neighbourhood; words 2 and 3 give a double     */
 /* r in [0, tot) with 53 random bits, and the roulette is the paper's:       */
 /* r < eps migration, r < eps + sel interaction, else reproduction.          */
 /* ------------------------------------------------------------------------ */
 static void o1_step(uint32_t L, uint32_t S, const uint8_t *D, double ex,
                     double sel, double tot, uint64_t seed, uint32_t replica,
-                    int rounds, uint64_t k, uint8_t *grid)
+                    int rounds, int nbhd, uint64_t k, uint8_t *grid)
 {
     uint32_t ctr[4] = {(uint32_t)k, (uint32_t)(k >> 32), TAG_RSU << 8, replica};
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
@@ -378,11 +395,17 @@ static void o1_step(uint32_t L, uint32_t S, const uint8_t *D, double ex,
     uint64_t i = ((uint64_t)w[0] * N) >> 32;
     uint32_t row = (uint32_t)(i / L), col = (uint32_t)(i % L);
     uint32_t nr = row, nc = col;
-    switch (w[1] & 3u) {
-    case 0: nr = (row + L - 1) % L; break; /* up */
-    case 1: nr = (row + 1) % L; break;     /* down */
-    case 2: nc = (col + L - 1) % L; break; /* left */
-    default: nc = (col + 1) % L; break;    /* right */
+    uint32_t up = (row + L - 1) % L, down = (row + 1) % L;
+    uint32_t left = (col + L - 1) % L, right = (col + 1) % L;
+    switch (nbhd == 8 ? (w[1] & 7u) : (w[1] & 3u)) {
+    case 0: nr = up; break;
+    case 1: nr = down; break;
+    case 2: nc = left; break;
+    case 3: nc = right; break;
+    case 4: nr = up; nc = left; break;
+    case 5: nr = up; nc = right; break;
+    case 6: nr = down; nc = left; break;
+    default: nr = down; nc = right; break;
     }
     uint64_t ni = (uint64_t)nr * L + nc;
     uint64_t bits53 = ((uint64_t)(w[2] >> 5) << 26) | (uint64_t)(w[3] >> 6);
@@ -399,8 +422,8 @@ static void o1_step(uint32_t L, uint32_t S, const uint8_t *D, double ex,
 
 void orc_o1_run(uint32_t L, uint32_t S, const uint8_t *D, double ex,
                 double sel, double rep, uint64_t seed, uint32_t replica,
-                int rounds, uint32_t mcs0, uint32_t n_mcs, uint8_t *grid,
-                uint32_t *counts)
+                int rounds, int nbhd, uint32_t mcs0, uint32_t n_mcs,
+                uint8_t *grid, uint32_t *counts)
 {
     uint64_t N = (uint64_t)L * L;
     double tot = (ex + sel) + rep;
@@ -409,7 +432,8 @@ void orc_o1_run(uint32_t L, uint32_t S, const uint8_t *D, double ex,
     for (uint32_t m = 0; m < n_mcs; ++m) {
         uint64_t k0 = (uint64_t)(mcs0 + m) * N;
         for (uint64_t n = 0; n < N; ++n)
-            o1_step(L, S, D, ex, sel, tot, seed, replica, rounds, k0 + n, grid);
+            o1_step(L, S, D, ex, sel, tot, seed, replica, rounds, nbhd, k0 + n,
+                    grid);
         if (counts)
             orc_counts(L, S, grid, counts + (size_t)(m + 1) * (S + 1));
     }
@@ -419,17 +443,19 @@ void orc_o1_run(uint32_t L, uint32_t S, const uint8_t *D, double ex,
  * k0 .. k0 + n - 1 of the O1 stream. */
 void orc_o1_steps(uint32_t L, uint32_t S, const uint8_t *D, double ex,
                   double sel, double rep, uint64_t seed, uint32_t replica,
-                  int rounds, uint64_t k0, uint64_t n, uint8_t *grid)
+                  int rounds, int nbhd, uint64_t k0, uint64_t n,
+                  uint8_t *grid)
 {
     double tot = (ex + sel) + rep;
     for (uint64_t k = 0; k < n; ++k)
-        o1_step(L, S, D, ex, sel, tot, seed, replica, rounds, k0 + k, grid);
+        o1_step(L, S, D, ex, sel, tot, seed, replica, rounds, nbhd, k0 + k,
+                grid);
 }
 
 void orc_o1_run_until(uint32_t L, uint32_t S, const uint8_t *D, double ex,
                       double sel, double rep, uint64_t seed, uint32_t replica,
-                      int rounds, uint32_t mcs0, uint32_t max_mcs, int mode,
-                      uint8_t *grid, uint32_t *result)
+                      int rounds, int nbhd, uint32_t mcs0, uint32_t max_mcs,
+                      int mode, uint8_t *grid, uint32_t *result)
 {
     uint64_t N = (uint64_t)L * L;
     double tot = (ex + sel) + rep;
@@ -440,7 +466,8 @@ void orc_o1_run_until(uint32_t L, uint32_t S, const uint8_t *D, double ex,
     while (!met && t < max_mcs) {
         uint64_t k0 = (uint64_t)(mcs0 + t) * N;
         for (uint64_t n = 0; n < N; ++n)
-            o1_step(L, S, D, ex, sel, tot, seed, replica, rounds, k0 + n, grid);
+            o1_step(L, S, D, ex, sel, tot, seed, replica, rounds, nbhd, k0 + n,
+                    grid);
         t++;
         orc_counts(L, S, grid, c);
         met = stop_met(S, c, mode);

@@ -16,6 +16,9 @@ streams (replica ids) and compared by a G-test.
 * L = 3: the RSU chain on 4^9 states with distinct up/down/left/right.
 * L = 4: one O2 pass is a uniform mixture over the four block offsets of
   independent per-block updates.
+* The same three pins for the 8-way Moore neighbourhood (the paper's
+  --neighbourhood 8), whose random-sequential step picks one of eight
+  neighbours.
 """
 import itertools
 
@@ -48,9 +51,19 @@ def g_test(observed: dict, expected_p: dict, n: int, min_e: float = 5.0):
     return chi2.sf(G, df)
 
 
-def rsu_step_dist(L, S, D, rates, dist):
+def neighbours(r, c, L, nbhd):
+    """The 4 von Neumann or 8 Moore neighbours of (r, c) under wrap (with
+    repeats on tiny lattices, as a uniform choice of direction gives)."""
+    d = [(-1, 0), (1, 0), (0, -1), (0, 1)]
+    if nbhd == 8:
+        d += [(-1, -1), (-1, 1), (1, -1), (1, 1)]
+    return [((r + dr) % L, (c + dc) % L) for dr, dc in d]
+
+
+def rsu_step_dist(L, S, D, rates, dist, nbhd=4):
     """One random-sequential step applied to a distribution over lattices
-    (dict tuple -> prob).  Neighbours: up, down, left, right with wrap."""
+    (dict tuple -> prob): a uniform cell, a uniform one of its nbhd
+    neighbours (direction chosen uniformly, wrap), an action by rate."""
     ex, sel, rep = rates
     tot = ex + sel + rep
     pa = {O.EXCHANGE: ex / tot, O.SELECTION: sel / tot,
@@ -60,8 +73,7 @@ def rsu_step_dist(L, S, D, rates, dist):
     for state, p in dist.items():
         for i in range(N):
             r, c = divmod(i, L)
-            for nr, nc in (((r - 1) % L, c), ((r + 1) % L, c),
-                           (r, (c - 1) % L), (r, (c + 1) % L)):
+            for nr, nc in neighbours(r, c, L, nbhd):
                 j = nr * L + nc
                 for a, q in pa.items():
                     if q == 0.0:
@@ -69,7 +81,7 @@ def rsu_step_dist(L, S, D, rates, dist):
                     s = list(state)
                     s[i], s[j] = _prose_rule(a, s[i], s[j], D)
                     t = tuple(s)
-                    out[t] = out.get(t, 0.0) + p * q / (4 * N)
+                    out[t] = out.get(t, 0.0) + p * q / (nbhd * N)
     return out
 
 
@@ -145,11 +157,14 @@ def test_L3_rsu_matches_exact_chain():
     assert g_test(sample(run, n), dist, n) > 1e-4
 
 
-def block_pass_dist(L, S, D, rates, g0):
+def block_pass_dist(L, S, D, rates, g0, nbhd=4):
     """Exact law of one O2 pass from g0: offsets uniform on {0,1}^2; the
-    (L/2)^2 disjoint 2x2 blocks update independently, each on a uniform one
-    of its 4 internal edges with a uniform orientation and an action drawn
-    with probability proportional to the rates."""
+    (L/2)^2 disjoint 2x2 blocks update independently, each on one of its
+    internal pairs with a uniform orientation and an action drawn with
+    probability proportional to the rates.  Von Neumann: the 4 edges, each
+    1/4.  Moore: the 4 edges 1/8 each and the 2 diagonals 1/4 each (a
+    diagonal lies in a block for one offset in four, an edge for one in
+    two, so these weights give every Moore pair the same rate)."""
     ex, sel, rep = rates
     tot = ex + sel + rep
     pa = [(O.EXCHANGE, ex / tot), (O.SELECTION, sel / tot),
@@ -164,14 +179,19 @@ def block_pass_dist(L, S, D, rates, g0):
                             r1 * L + c1)
             sites = (A, B, C_, Dd)
             outcomes = {}
-            for (f, s) in ((A, B), (C_, Dd), (A, C_), (B, Dd)):
+            pairs = [((A, B), 1), ((C_, Dd), 1), ((A, C_), 1), ((B, Dd), 1)]
+            if nbhd == 8:
+                pairs += [((A, Dd), 2), ((B, C_), 2)]
+            wsum = sum(wt for _, wt in pairs)
+            for (f, s), wt in pairs:
                 for cell, nbr in ((f, s), (s, f)):
                     for a, q in pa:
                         loc = {k: int(g0[k]) for k in sites}
                         loc[cell], loc[nbr] = _prose_rule(a, loc[cell],
                                                           loc[nbr], D)
                         key = tuple(loc[k] for k in sites)
-                        outcomes[key] = outcomes.get(key, 0.0) + q / 8
+                        outcomes[key] = (outcomes.get(key, 0.0) +
+                                         q * wt / (2 * wsum))
             per_block.append((sites, outcomes))
         joint = {tuple(g0.tolist()): 1.0}
         for sites, outcomes in per_block:
@@ -208,6 +228,112 @@ def test_L4_one_pass_matches_exact_block_law(mutual):
         O.o2_pass(job, g, 3, rep % 4)
         return g
     assert g_test(sample(run, n), dist, n) > 1e-4
+
+
+# --- Moore (8-way) neighbourhood ------------------------------------------
+# On L = 2 a site's eight Moore neighbours are its row neighbour twice, its
+# column neighbour twice and its diagonal neighbour four times, so a
+# random-sequential step picks each axis edge with probability 1/8 and each
+# diagonal with 1/4: exactly the slot weights of one 2x2 block.  One O2 MCS
+# therefore has the law of four RSU steps here too.
+
+
+@pytest.mark.parametrize("mutual", [False, True])
+def test_L2_moore_rsu_matches_exact_chain(mutual):
+    L, S = 2, 3
+    D = D_MUTUAL if mutual else O.circulant_matrix(S, [1])
+    rates = (1.0, 1.0, 2.0)
+    g0 = np.array([1, 2, 0, 3], np.uint8)
+    dist = {tuple(g0.tolist()): 1.0}
+    for _ in range(4):
+        dist = rsu_step_dist(L, S, D, rates, dist, nbhd=8)
+    n = 20000
+
+    def run(rep):
+        job = O.Job(L, S, D, *rates, seed=13, replica=rep, nbhd=8)
+        g = g0.copy()
+        O.o1_steps(job, g, 0, 4)
+        return g
+    assert g_test(sample(run, n), dist, n) > 1e-4
+
+
+@pytest.mark.parametrize("rates", RATES)
+@pytest.mark.parametrize("mutual", [False, True])
+def test_L2_moore_block_schedule_mcs_equals_four_rsu_steps(rates, mutual):
+    L, S = 2, 3
+    D = D_MUTUAL if mutual else O.circulant_matrix(S, [1])
+    g0 = np.array([3, 0, 2, 1], np.uint8)
+    dist = {tuple(g0.tolist()): 1.0}
+    for _ in range(8):
+        dist = rsu_step_dist(L, S, D, rates, dist, nbhd=8)
+    n = 20000
+
+    def run(rep):
+        job = O.Job(L, S, D, *rates, seed=6, replica=rep, nbhd=8)
+        g = g0.copy()
+        O.o2_run(job, g, 4, 2, want_counts=False)
+        return g
+    assert g_test(sample(run, n), dist, n) > 1e-4
+
+
+def test_L3_moore_rsu_matches_exact_chain():
+    # eight distinct neighbours on L = 3
+    L, S = 3, 3
+    D = O.circulant_matrix(S, [1])
+    rates = (1.0, 1.0, 2.0)
+    g0 = np.array([1, 2, 3, 0, 1, 2, 3, 0, 2], np.uint8)
+    dist = {tuple(g0.tolist()): 1.0}
+    for _ in range(3):
+        dist = rsu_step_dist(L, S, D, rates, dist, nbhd=8)
+    n = 30000
+
+    def run(rep):
+        job = O.Job(L, S, D, *rates, seed=4, replica=rep, nbhd=8)
+        g = g0.copy()
+        O.o1_steps(job, g, 500, 3)
+        return g
+    assert g_test(sample(run, n), dist, n) > 1e-4
+
+
+@pytest.mark.parametrize("mutual", [False, True])
+def test_L4_moore_one_pass_matches_exact_block_law(mutual):
+    L, S = 4, 3
+    D = D_MUTUAL if mutual else O.circulant_matrix(S, [1])
+    rates = (1.0, 1.0, 2.0)
+    g0 = np.array([1, 2, 0, 3,
+                   3, 3, 1, 0,
+                   0, 2, 2, 1,
+                   1, 0, 3, 2], np.uint8)
+    dist = block_pass_dist(L, S, D, rates, g0, nbhd=8)
+    assert abs(sum(dist.values()) - 1.0) < 1e-9
+    n = 40000
+
+    def run(rep):
+        job = O.Job(L, S, D, *rates, seed=10, replica=rep, nbhd=8)
+        g = g0.copy()
+        O.o2_pass(job, g, 3, rep % 4)
+        return g
+    assert g_test(sample(run, n), dist, n) > 1e-4
+
+
+def test_moore_law_differs_from_von_neumann():
+    # the Moore pins are not the von Neumann ones under another name: the
+    # exact one-pass laws differ, and Moore samples reject the 4-way law
+    L, S = 4, 3
+    D = O.circulant_matrix(S, [1])
+    rates = (1.0, 1.0, 2.0)
+    g0 = np.array([1, 2, 0, 3, 3, 3, 1, 0, 0, 2, 2, 1, 1, 0, 3, 2], np.uint8)
+    vn = block_pass_dist(L, S, D, rates, g0, nbhd=4)
+    n = 40000
+
+    def run(rep):
+        job = O.Job(L, S, D, *rates, seed=10, replica=rep, nbhd=8)
+        g = g0.copy()
+        O.o2_pass(job, g, 3, rep % 4)
+        return g
+    obs = sample(run, n)
+    vn = {k: vn.get(k, 0.0) + 1e-12 for k in set(vn) | set(obs)}
+    assert g_test(obs, vn, n) < 1e-6
 
 
 def test_g_test_detects_a_planted_rule_error():

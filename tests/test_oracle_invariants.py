@@ -9,17 +9,19 @@ from paper_2508_16639_amd.workloads import random_lattice
 RUNNERS = {"O1": O.o1_run, "O2": O.o2_run}
 
 
-def _job(L, S, K, ex=0.7, sel=1.0, rep=1.0, seed=3, replica=0, D=None):
+def _job(L, S, K, ex=0.7, sel=1.0, rep=1.0, seed=3, replica=0, D=None,
+         nbhd=4):
     if D is None:
         D = O.circulant_matrix(S, K)
-    return O.Job(L, S, D, ex, sel, rep, seed=seed, replica=replica)
+    return O.Job(L, S, D, ex, sel, rep, seed=seed, replica=replica, nbhd=nbhd)
 
 
+@pytest.mark.parametrize("nbhd", [4, 8])
 @pytest.mark.parametrize("which", ["O1", "O2"])
 @pytest.mark.parametrize("S,K", [(3, [1]), (5, [1, 3])])
-def test_counts_conserve_sites_and_values_stay_in_range(which, S, K):
+def test_counts_conserve_sites_and_values_stay_in_range(which, S, K, nbhd):
     L = 24
-    job = _job(L, S, K)
+    job = _job(L, S, K, nbhd=nbhd)
     g = job.init()
     c0 = O.counts(g, L, S)
     c = RUNNERS[which](job, g, 0, 30)
@@ -34,10 +36,11 @@ def test_counts_conserve_sites_and_values_stay_in_range(which, S, K):
             assert (c[z[0]:, s] == 0).all()
 
 
+@pytest.mark.parametrize("nbhd", [4, 8])
 @pytest.mark.parametrize("which", ["O1", "O2"])
-def test_exchange_only_permutes_sites(which):
+def test_exchange_only_permutes_sites(which, nbhd):
     L, S = 16, 5
-    job = _job(L, S, [1, 3], ex=1.0, sel=0.0, rep=0.0)
+    job = _job(L, S, [1, 3], ex=1.0, sel=0.0, rep=0.0, nbhd=nbhd)
     g = random_lattice(L, S, seed=4)
     before = np.sort(g.copy())
     c = RUNNERS[which](job, g, 5, 40)
@@ -68,13 +71,14 @@ def test_empty_count_monotone_under_single_actions(which):
     assert (np.diff(c[:, 0].astype(np.int64)) >= 0).all()   # I6 selection
 
 
+@pytest.mark.parametrize("nbhd", [4, 8])
 @pytest.mark.parametrize("which", ["O1", "O2"])
 @pytest.mark.parametrize("S,K", [(3, [1]), (5, [1, 3])])
-def test_cyclic_relabel_commutes_bit_exactly(which, S, K):
+def test_cyclic_relabel_commutes_bit_exactly(which, S, K, nbhd):
     # i -> i+1 (mod S) on species, 0 fixed, is an automorphism of C(S, K);
     # the random draws do not depend on labels, so the runs map exactly.  (I7)
     L = 16
-    job = _job(L, S, K, ex=0.9)
+    job = _job(L, S, K, ex=0.9, nbhd=nbhd)
     g = random_lattice(L, S, seed=21)
     rot = np.array([0] + [(s % S) + 1 for s in range(1, S + 1)], np.uint8)
     a = g.copy()
@@ -104,10 +108,11 @@ def test_rpsls_offset_sets_are_isomorphic(which):
     assert np.array_equal(phi[a], b)
 
 
+@pytest.mark.parametrize("nbhd", [4, 8])
 @pytest.mark.parametrize("which", ["O1", "O2"])
-def test_resume_split_equals_straight_run(which):
+def test_resume_split_equals_straight_run(which, nbhd):
     L, S = 20, 3
-    job = _job(L, S, [1])
+    job = _job(L, S, [1], nbhd=nbhd)
     g = job.init()
     a = g.copy()
     ca = RUNNERS[which](job, a, 0, 25)

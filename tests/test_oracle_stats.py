@@ -1,11 +1,13 @@
 """Statistical agreement of the block schedule (O2) with the paper's
-random-sequential update (O1) on RPS, beyond the exact small-lattice laws.
+random-sequential update (O1) on RPS, beyond the exact small-lattice laws,
+for the von Neumann and (densities) the Moore neighbourhood.
 
 Tolerances: differences of means within 4 standard errors of the difference
 (floor 0.005 for densities); deterministic seeds, so the outcome is fixed."""
 from multiprocessing import Pool
 
 import numpy as np
+import pytest
 from scipy.stats import ks_2samp
 
 import oracle as O
@@ -23,9 +25,9 @@ def _extinction(args):
 
 
 def _densities(args):
-    which, L, M, T, rep = args
+    which, L, M, T, rep, nbhd = args
     job = O.Job(L, 3, O.circulant_matrix(3, [1]), eps_from_mobility(M, L),
-                seed=2, replica=rep)
+                seed=2, replica=rep, nbhd=nbhd)
     g = job.init()
     f = O.o2_run if which == 2 else O.o1_run
     c = f(job, g, 0, T)
@@ -45,11 +47,14 @@ def test_extinction_probability_o1_vs_o2():
     assert ks_2samp(r1[:, 1], r2[:, 1]).pvalue > 1e-4
 
 
-def test_mean_densities_o1_vs_o2():
+@pytest.mark.parametrize("nbhd", [4, 8])
+def test_mean_densities_o1_vs_o2(nbhd):
     L, M, T, R = 64, 1e-5, 200, 240
     with Pool(8) as p:
-        d2 = np.array(p.map(_densities, [(2, L, M, T, i) for i in range(R)]))
-        d1 = np.array(p.map(_densities, [(1, L, M, T, i) for i in range(R)]))
+        d2 = np.array(p.map(_densities,
+                            [(2, L, M, T, i, nbhd) for i in range(R)]))
+        d1 = np.array(p.map(_densities,
+                            [(1, L, M, T, i, nbhd) for i in range(R)]))
     diff = np.abs(d1.mean(0) - d2.mean(0))
     se = np.sqrt(d1.var(0, ddof=1) / R + d2.var(0, ddof=1) / R)
     assert (diff <= np.maximum(4 * se, 0.005)).all(), (diff, se)
