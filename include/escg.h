@@ -81,8 +81,18 @@ typedef struct escg_params {
     double   rate_rep; /* reproduction rate >= 0, finite; sum > 0           */
     uint64_t seed;     /* Philox key                                        */
     uint32_t replica;  /* independent stream id under the same seed         */
-    uint32_t reserved; /* must be 0                                         */
+    uint32_t flags;    /* ESCG_FLAG_*; other bits must be 0                 */
 } escg_params;
+
+/* flags: the 8-way Moore neighbourhood instead of the 4-way von Neumann one
+ * (the paper's --neighbourhood option, Sec. "Single Threaded ESCG in C++").
+ * A random-sequential step then picks one of a site's eight neighbours; in
+ * the block schedule a block word's bits 0-2 pick one of eight pair slots,
+ * the four axis edges (A,B), (C,D), (A,C), (B,D) once each and the two
+ * diagonals (A,D), (B,C) twice each, and bit 3 the orientation, which
+ * updates every one of the 4N Moore pairs at the same rate, 1/16 per
+ * pass. */
+#define ESCG_FLAG_MOORE 1u
 
 /* Human-readable name of a status code (static storage). */
 const char *escg_status_str(escg_status s);

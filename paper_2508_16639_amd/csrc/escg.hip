@@ -51,7 +51,7 @@ struct JobDev {
     uint32_t *result;     // optional {flag, t_ext, counts[0..S]}
     uint32_t L, S, T1, T2;
     uint32_t replica, mcs0, max_mcs, mode;
-    uint32_t init, result_words, pad0, pad1;
+    uint32_t init, result_words, moore, pad1;
     uint32_t dom[32];
 };
 
@@ -128,7 +128,7 @@ __device__ void run_job_lds(const JobDev &J, uint8_t *base, uint8_t *smem,
     const uint32_t k0 = (uint32_t)J.seed, k1 = (uint32_t)(J.seed >> 32);
     uint8_t *g = base + J.lat_off;
 
-    setup_tables(TB, J.dom);
+    setup_tables(TB, J.dom, J.moore != 0);
     // row padding bytes match no species
     if (LS != L)
         for (uint32_t r = tid; r < L; r += nt)
@@ -265,7 +265,7 @@ struct TileArgs {
     const uint32_t *done; // non-null and nonzero: only copy src to dst
     uint64_t seed;
     uint64_t dom_packed;
-    uint32_t L, S, T1, T2, replica, t;
+    uint32_t L, S, T1, T2, replica, t, moore;
     uint32_t dom[32];
 };
 
@@ -362,10 +362,10 @@ __global__ __launch_bounds__(kTileThreads) void tile_mcs_kernel(TileArgs a)
                     const uint32_t pA = lr * LS + lc;
                     if (kPacked)
                         update_block(lat, pA, pA + 1, pA + LS, pA + LS + 1, w,
-                                     a.T1, a.T2, dp);
+                                     a.T1, a.T2, dp, a.moore != 0);
                     else
                         update_block(lat, pA, pA + 1, pA + LS, pA + LS + 1, w,
-                                     a.T1, a.T2, dt);
+                                     a.T1, a.T2, dt, a.moore != 0);
                 }
             }
         }
@@ -437,7 +437,7 @@ struct TiledArgs {
     uint32_t *counts;   // rows (n+1)*(S+1) with rows 1..n zeroed, or null
     uint64_t seed;
     TileGeom G;
-    uint32_t S, T1, T2, replica, mcs0, n_mcs, spin_limit;
+    uint32_t S, T1, T2, replica, mcs0, n_mcs, spin_limit, moore;
     uint32_t dom[32];
 };
 
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
     if (tid == 0)
         s_misc[0] = 0;
     tile_load(lat, a.lattice, G, ty, tx);
-    setup_tables(TB, a.dom); // ends with a barrier
+    setup_tables(TB, a.dom, a.moore != 0); // ends with a barrier
     const QuadCtx qc = make_quad_ctx(TB, a.T1, a.T2);
     const TileWalk W = tile_walk(G, ty, tx);
 
@@ -517,7 +517,7 @@ struct StepArgs {
     const uint32_t *done; // non-null and nonzero: only carry src to dst
     uint64_t seed;
     TileGeom G;
-    uint32_t S, T1, T2, replica, t;
+    uint32_t S, T1, T2, replica, t, moore;
     uint32_t dom[32];
 };
 
@@ -542,7 +542,7 @@ __global__ __launch_bounds__(512) void tiled_step_kernel(StepArgs a)
         return;
     }
     tile_load(lat, a.src, G, ty, tx);
-    setup_tables(TB, a.dom);
+    setup_tables(TB, a.dom, a.moore != 0);
     const QuadCtx qc = make_quad_ctx(TB, a.T1, a.T2);
     tile_mcs(lat, G, tile_walk(G, ty, tx), a.t, a.replica, (uint32_t)a.seed,
              (uint32_t)(a.seed >> 32), qc);
@@ -568,7 +568,7 @@ struct BatchStepJob {
     uint64_t seed;
     TileGeom G;
     uint32_t S, T1, T2, replica, t0;
-    uint32_t wg0;
+    uint32_t wg0, moore;
     uint32_t dom[32];
 };
 
@@ -597,7 +597,7 @@ __global__ __launch_bounds__(kBatchStepThreads) void tiled_step_batch_kernel(
     uint8_t *dst = (k & 1u) ? J.lattice : J.scratch;
     uint8_t *lat = smem;
     tile_load(lat, src, G, ty, tx);
-    setup_tables(TB, J.dom);
+    setup_tables(TB, J.dom, J.moore != 0);
     const QuadCtx qc = make_quad_ctx(TB, J.T1, J.T2);
     tile_mcs(lat, G, tile_walk(G, ty, tx), J.t0 + k, J.replica,
              (uint32_t)J.seed, (uint32_t)(J.seed >> 32), qc);
@@ -722,7 +722,7 @@ escg_status validate(const escg_params *p)
         return ESCG_EINVAL;
     if (p->S < 1 || p->S > ESCG_MAX_SPECIES)
         return ESCG_EINVAL;
-    if (p->reserved != 0)
+    if (p->flags & ~ESCG_FLAG_MOORE)
         return ESCG_EINVAL;
     const double r[3] = {p->rate_ex, p->rate_sel, p->rate_rep};
     for (double v : r)
@@ -854,6 +854,7 @@ JobDev make_job(const escg_params *p, const Derived &d, uint64_t off,
     J.mode = mode;
     J.init = init;
     J.result_words = result_words;
+    J.moore = (p->flags & ESCG_FLAG_MOORE) ? 1u : 0u;
     for (int i = 0; i < 32; ++i)
         J.dom[i] = p->dom[i];
     return J;
@@ -923,6 +924,7 @@ TileArgs tile_args(const escg_params *p, const Derived &d)
     a.T1 = d.T1;
     a.T2 = d.T2;
     a.replica = p->replica;
+    a.moore = (p->flags & ESCG_FLAG_MOORE) ? 1u : 0u;
     for (int i = 0; i < 32; ++i)
         a.dom[i] = p->dom[i];
     return a;
@@ -1134,6 +1136,7 @@ StepArgs step_args(const escg_params *p, const Derived &d,
     a.T1 = d.T1;
     a.T2 = d.T2;
     a.replica = p->replica;
+    a.moore = (p->flags & ESCG_FLAG_MOORE) ? 1u : 0u;
     for (int i = 0; i < 32; ++i)
         a.dom[i] = p->dom[i];
     return a;
@@ -1187,6 +1190,7 @@ escg_status run_tiled_persistent(const escg_params *p, const Derived &d,
     a.mcs0 = mcs0;
     a.n_mcs = n_mcs;
     a.spin_limit = 1u << 22; // polls (seconds), then abort with an error
+    a.moore = (p->flags & ESCG_FLAG_MOORE) ? 1u : 0u;
     for (int i = 0; i < 32; ++i)
         a.dom[i] = p->dom[i];
     // slot 0 tagged 0, slot 1 tagged 1: neither matches its first use
@@ -1726,6 +1730,7 @@ escg_status escg_step_batch(uint32_t n, const escg_params *h_params,
             J.replica = p->replica;
             J.t0 = h_mcs0[j];
             J.wg0 = wg;
+            J.moore = (p->flags & ESCG_FLAG_MOORE) ? 1u : 0u;
             for (int q = 0; q < 32; ++q)
                 J.dom[q] = p->dom[q];
             wg += J.G.TY * J.G.TX;

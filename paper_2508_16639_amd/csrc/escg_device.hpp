@@ -155,18 +155,26 @@ __device__ __forceinline__ void pair_rule(uint32_t u, uint32_t T1, uint32_t T2,
 }
 
 // Updates one 2x2 block in LDS.  pA..pD are the LDS byte offsets of the
-// block's top-left, top-right, bottom-left and bottom-right sites.
+// block's top-left, top-right, bottom-left and bottom-right sites.  Von
+// Neumann: bits 0-1 of w pick the edge, bit 2 the orientation; Moore: bits
+// 0-2 pick one of the eight pair slots (edges, then the diagonals (A,D),
+// (B,C) twice each), bit 3 the orientation.
 template <class Dom>
 __device__ __forceinline__ void update_block(uint8_t *lat, uint32_t pA,
                                              uint32_t pB, uint32_t pC,
                                              uint32_t pD, uint32_t w,
                                              uint32_t T1, uint32_t T2,
-                                             const Dom &d)
+                                             const Dom &d, bool moore)
 {
-    const uint32_t e = w & 3u;
-    uint32_t f = (e & 2u) ? ((e & 1u) ? pB : pA) : ((e & 1u) ? pC : pA);
-    uint32_t s = (e & 2u) ? ((e & 1u) ? pD : pC) : ((e & 1u) ? pD : pB);
-    if (w & 4u) {
+    const uint32_t e = moore ? (w & 7u) : (w & 3u);
+    const uint32_t o = moore ? (w >> 3) & 1u : (w >> 2) & 1u;
+    // value selects (not lvalue ?:, which would select addresses)
+    uint32_t f = (e & 1u) ? pC : pA, s = (e & 1u) ? pD : pB;     // 0, 1
+    f = (e == 2) ? pA : (e == 3) ? pB : f;                       // 2, 3
+    s = (e == 2) ? pC : (e == 3) ? pD : s;
+    f = (e >= 4) ? ((e & 1u) ? pB : pA) : f;                     // 4..7
+    s = (e >= 4) ? ((e & 1u) ? pC : pD) : s;
+    if (o) {
         const uint32_t t = f;
         f = s;
         s = t;

@@ -137,16 +137,18 @@ __device__ inline QuadCtx make_quad_ctx(const LdsTables<SP> &T, uint32_t T1,
     return qc;
 }
 
-// Fills the tables of a job (dominance masks from `dom`, global or LDS).
+// Fills the tables of a job (dominance masks from `dom`, global or LDS;
+// `moore`: the 8-way neighbourhood's pair slots).
 template <int SP>
-__device__ inline void setup_tables(LdsTables<SP> &T, const uint32_t *dom)
+__device__ inline void setup_tables(LdsTables<SP> &T, const uint32_t *dom,
+                                    bool moore)
 {
     for (uint32_t i = threadIdx.x; i < 32; i += blockDim.x)
         T.dom[i] = dom[i];
     for (uint32_t i = threadIdx.x; i < 64; i += blockDim.x)
         T.cnt[i] = 0;
     __syncthreads();
-    build_quad_luts(T.sel, T.rule, SP, T.dom);
+    build_quad_luts(T.sel, T.rule, SP, T.dom, moore);
     __syncthreads();
 }
 

@@ -9,7 +9,9 @@
 //     gather selector moves (selected cell, neighbour) = (x, y) into bytes
 //     0 and 1; the scatter selector writes (x', y') back into their places
 //     and keeps the other two sites.  Bits 0-1 (edge) and 2 (orientation)
-//     decide them; bits 3-7 are unused, so the table repeats every 8 entries.
+//     decide them in the von Neumann neighbourhood, bits 0-2 (pair) and 3
+//     (orientation) in the Moore one; the other bits are unused, so the
+//     table repeats every 8 or 16 entries.
 //   * the action is picked by comparing w with thresholds pre-shifted into
 //     word space (u = w >> 8 < T  <=>  w <= (T << 8) - 1), which selects
 //     one of three rule tables;
@@ -64,14 +66,28 @@ __host__ __device__ inline ActionSplit split_actions(uint32_t T1, uint32_t T2)
 
 // Builds the selector table (2 KB) and the rule tables (3*Sp*Sp u16) in LDS
 // with the workgroup's threads.  dom: 32 dominance masks (LDS or global).
+// Von Neumann: bits 0-1 of the block word pick the edge, bit 2 the
+// orientation.  Moore: bits 0-2 pick one of eight pair slots (the four
+// edges, then the diagonals (A,D), (B,C) twice each), bit 3 the orientation.
 __device__ inline void build_quad_luts(uint2 *sel, uint16_t *rule, uint32_t Sp,
-                                       const uint32_t *dom)
+                                       const uint32_t *dom, bool moore)
 {
     for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) {
-        const uint32_t e = i & 3u, o = (i >> 2) & 1u;
-        // edge sites as byte positions of B = [A, B, C, D]
-        const uint32_t f = (e == 0) ? 0u : (e == 1) ? 2u : (e == 2) ? 0u : 1u;
-        const uint32_t s = (e == 0) ? 1u : (e == 1) ? 3u : (e == 2) ? 2u : 3u;
+        const uint32_t e = moore ? (i & 7u) : (i & 3u);
+        const uint32_t o = moore ? (i >> 3) & 1u : (i >> 2) & 1u;
+        // pair sites as byte positions of B = [A, B, C, D]
+        const uint32_t f = (e == 0)   ? 0u
+                           : (e == 1) ? 2u
+                           : (e == 2) ? 0u
+                           : (e == 3) ? 1u
+                           : (e & 1u) ? 1u   // (B, C)
+                                      : 0u;  // (A, D)
+        const uint32_t s = (e == 0)   ? 1u
+                           : (e == 1) ? 3u
+                           : (e == 2) ? 2u
+                           : (e == 3) ? 3u
+                           : (e & 1u) ? 2u
+                                      : 3u;
         const uint32_t cell = o ? s : f, nbr = o ? f : s;
         const uint32_t gather = cell | (nbr << 8) | 0x0C0C0000u;
         uint32_t scatter = 0;

@@ -24,6 +24,7 @@ ROUTE_LDS, ROUTE_TILED, ROUTE_PERSISTENT = 1, 2, 3
 ROUTE_NAMES = {0: "none", 1: "lds", 2: "tiled", 3: "persistent"}
 STOP_FIRST_EXTINCTION, STOP_MONOCULTURE, STOP_NONE = 0, 1, 2
 BATCH_RESULT_WORDS = 34
+FLAG_MOORE = 1           # ESCG_FLAG_MOORE: 8-way neighbourhood
 MAX_SPECIES = 31
 
 
@@ -41,7 +42,7 @@ class CParams(C.Structure):
                 ("dom", C.c_uint32 * 32),
                 ("rate_ex", C.c_double), ("rate_sel", C.c_double),
                 ("rate_rep", C.c_double), ("seed", C.c_uint64),
-                ("replica", C.c_uint32), ("reserved", C.c_uint32)]
+                ("replica", C.c_uint32), ("flags", C.c_uint32)]
 
 
 EXPORTS = ("escg_status_str", "escg_last_error", "escg_circulant_dom", "escg_dom_from_matrix",
@@ -138,6 +139,7 @@ class Params:
     rep: float = 1.0
     seed: int = 1
     replica: int = 0
+    moore: bool = False      # 8-way (Moore) instead of 4-way neighbourhood
 
     def c(self) -> CParams:
         p = CParams()
@@ -148,7 +150,7 @@ class Params:
                                              float(self.rep))
         p.seed = int(self.seed) & 0xFFFFFFFFFFFFFFFF
         p.replica = int(self.replica) & 0xFFFFFFFF
-        p.reserved = 0
+        p.flags = FLAG_MOORE if self.moore else 0
         return p
 
 

@@ -6,13 +6,15 @@ import oracle as O
 from paper_2508_16639_amd import escg
 
 
-def pair(L, S, K, ex, sel=1.0, rep=1.0, seed=1, replica=0, D=None):
+def pair(L, S, K, ex, sel=1.0, rep=1.0, seed=1, replica=0, D=None,
+         moore=False):
     """The same job for the HIP library (escg.Params) and the oracle."""
     if D is None:
         D = O.circulant_matrix(S, K) if K else np.zeros((S, S), np.uint8)
     p = escg.Params(L=L, S=S, dom=escg.dom_from_matrix(D), ex=ex, sel=sel,
-                    rep=rep, seed=seed, replica=replica)
-    j = O.Job(L, S, D, ex, sel, rep, seed=seed, replica=replica)
+                    rep=rep, seed=seed, replica=replica, moore=moore)
+    j = O.Job(L, S, D, ex, sel, rep, seed=seed, replica=replica,
+              nbhd=8 if moore else 4)
     return p, j
 
 

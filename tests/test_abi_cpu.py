@@ -136,6 +136,24 @@ def test_batch_rejects_overlap_and_bad_jobs():
                               None) == escg.OK
 
 
+@pytest.mark.parametrize("flags", [2, 4, 0x80000000, 3])
+def test_unknown_flag_bits_rejected(flags):
+    cp = escg.Params(L=8, S=3, dom=escg.circulant_dom(3, [1]), ex=1.0).c()
+    cp.flags = flags
+    # validation precedes any device work: a fake (aligned) pointer is safe
+    assert escg.lib().escg_step_mcs(C.byref(cp), C.c_void_p(4096), 0, 1,
+                                    None, None) == escg.EINVAL
+
+
+def test_moore_flag_is_bit_zero():
+    assert escg.FLAG_MOORE == 1
+    cp = escg.Params(L=8, S=3, dom=escg.circulant_dom(3, [1]), ex=1.0,
+                     moore=True).c()
+    assert cp.flags == 1
+    src = open(os.path.join(ROOT, "include", "escg.h")).read()
+    assert re.search(r"#define ESCG_FLAG_MOORE 1u", src)
+
+
 def test_routing_knobs_and_limits_callable_without_gpu():
     # defaults: persistent kernel from L = 72 (L % 8 == 0), LDS otherwise
     assert escg.persistent_min_L() == 72

@@ -122,6 +122,75 @@ def test_step_mcs_bit_exact(case, route):
     assert np.array_equal(c, rc)
 
 
+MOORE_CASES = [
+    # L, S, K, (ex, sel, rep), n_mcs
+    (2, 3, [1], (1.0, 1.0, 1.0), 20),
+    (6, 5, [1, 3], (2.0, 1.0, 1.0), 10),
+    (16, 8, [1, 2, 5], (1.0, 0.5, 1.0), 8),
+    (64, 3, [1], (0.5, 1.0, 1.0), 8),
+    (100, 7, [1, 2, 4], (1.0, 1.0, 1.0), 4),
+    (130, 13, [1, 2, 5], (1.0, 1.0, 1.0), 3),
+    (200, 5, [1, 3], (51.2, 1.0, 1.0), 3),
+    (404, 5, [1, 3], (1.0, 1.0, 1.0), 2),
+    (520, 3, [1], (5.0, 1.0, 1.0), 2),
+]
+
+
+@pytest.mark.parametrize("case", MOORE_CASES, ids=lambda c: f"L{c[0]}_S{c[1]}")
+@pytest.mark.parametrize("route", ["auto", "tiled", "lds", "persistent"])
+def test_moore_step_mcs_bit_exact(case, route):
+    L, S, K, rates, n = case
+    if route in ("tiled", "persistent") and L < 16:
+        pytest.skip("tiled paths not used below L=16")
+    if route == "lds" and L > escg.batch_max_L(S):
+        pytest.skip("lattice does not fit LDS")
+    route_to(route)
+    p, j = pair(L, S, K, *rates, seed=L * 5 + S, replica=1, moore=True)
+    g0 = random_lattice(L, S, seed=L + 7, domain=2)
+    out, c = gpu_step(p, g0, 13, n, route=route)
+    ref = g0.copy()
+    rc = O.o2_run(j, ref, 13, n)
+    assert np.array_equal(out, ref)
+    assert np.array_equal(c, rc)
+
+
+def test_moore_differs_from_von_neumann_on_gpu():
+    p4, _ = pair(64, 3, [1], 1.0, seed=2)
+    p8, _ = pair(64, 3, [1], 1.0, seed=2, moore=True)
+    g0 = random_lattice(64, 3, seed=5)
+    a, _ = gpu_step(p4, g0, 0, 3)
+    b, _ = gpu_step(p8, g0, 0, 3)
+    assert not np.array_equal(a, b)
+
+
+def test_moore_step_batch_and_batch_run_match_oracle():
+    specs = [(16, 3, [1], 3), (136, 5, [1, 3], 2), (64, 13, [1, 2, 5], 1)]
+    ps, js, lats, g0s = [], [], [], []
+    for i, (L, S, K, n) in enumerate(specs):
+        p, j = pair(L, S, K, 0.9, seed=70 + i, replica=i, moore=True)
+        g0 = random_lattice(L, S, seed=i, domain=2)
+        ps.append(p)
+        js.append(j)
+        g0s.append(g0)
+        lats.append(dev(g0))
+    escg.step_batch(ps, lats, [4] * len(specs), [s[3] for s in specs])
+    for (L, S, K, n), j, g0, lat in zip(specs, js, g0s, lats):
+        ref = g0.copy()
+        O.o2_run(j, ref, 4, n)
+        assert np.array_equal(host(lat), ref), (L, S)
+    # batched LDS-resident path with a stop condition
+    p, j = pair(48, 3, [1], 2.0, seed=5, moore=True)
+    buf = torch.zeros(48 * 48, dtype=torch.uint8, device="cuda:0")
+    res = torch.full((escg.BATCH_RESULT_WORDS,), -1, dtype=torch.int32,
+                     device="cuda:0")
+    escg.batch_run([p], [0], buf, [300], escg.STOP_FIRST_EXTINCTION, True,
+                   res)
+    g = j.init()
+    r = O.o2_run_until(j, g, 0, 300, O.FIRST_EXTINCTION)
+    assert np.array_equal(host(res)[:6], r)
+    assert np.array_equal(host(buf), g)
+
+
 def _imported_matrices():
     """Dominance matrices that are not circulant: RPSLS with one edge of the
     five-species cycle removed, a pair of species that beat each other, and
