@@ -6,7 +6,7 @@
 The flags mirror the paper's program (Sec. "Single Threaded ESCG in C++",
 table of command-line parameters; CUDA section, additional flags):
 --length/--height (square lattices only), --mcs (MCS limit), --neighbourhood
-(4; the 8-way neighbourhood is not built), --printFrequency, --mobility
+(4 = von Neumann, 8 = Moore), --printFrequency, --mobility
 (eps = M * L^2 / 2, escg_eps_from_mobility), --species, --flux (periodic
 boundaries only), --empty (initial empty-site probability), --save,
 --dominance (import a dominance CSV; it sets the species count), --resume
@@ -111,6 +111,7 @@ class Run:
             g, L, done = escg_io.read_grid_csv(os.path.join(resume,
                                                             "grid.csv"))
             self.L, self.S = L, D.shape[0]
+            self.moore = int(prm.get("neighbourhood", "4")) == 8
             self.mobility = float(prm["mobility"])
             self.seed = int(prm["seed"])
             self.replica = int(prm["replica"])
@@ -123,9 +124,6 @@ class Run:
             if args.height is not None and args.height != args.length:
                 raise SystemExit("only square lattices: --height must equal "
                                  "--length")
-            if args.neighbourhood != 4:
-                raise SystemExit("the 8-way (Moore) neighbourhood is not "
-                                 "built; use --neighbourhood 4")
             if not args.flux:
                 raise SystemExit("only periodic boundaries (--flux true)")
             self.L = args.length
@@ -142,6 +140,7 @@ class Run:
                 self.D = np.array([[(dom[a] >> b) & 1
                                     for b in range(1, self.S + 1)]
                                    for a in range(1, self.S + 1)], np.uint8)
+            self.moore = args.neighbourhood == 8
             self.mobility = args.mobility
             self.seed, self.replica = args.seed, args.replica
             self.sel, self.rep = args.selection, args.reproduction
@@ -152,7 +151,7 @@ class Run:
         self.p = escg.Params(L=self.L, S=self.S,
                              dom=escg.dom_from_matrix(self.D), ex=eps,
                              sel=self.sel, rep=self.rep, seed=self.seed,
-                             replica=self.replica)
+                             replica=self.replica, moore=self.moore)
         self.lat = torch.empty(self.N, dtype=torch.uint8, device="cuda")
         if self.lattice0 is not None:
             if int(self.lattice0.max()) > self.S:
@@ -172,8 +171,8 @@ class Run:
         return {"length": self.L, "height": self.L, "species": self.S,
                 "mobility": repr(self.mobility), "seed": self.seed,
                 "replica": self.replica, "selection": repr(self.sel),
-                "reproduction": repr(self.rep), "neighbourhood": 4,
-                "flux": "true"}
+                "reproduction": repr(self.rep),
+                "neighbourhood": 8 if self.moore else 4, "flux": "true"}
 
     def host_lattice(self) -> np.ndarray:
         self.torch.cuda.synchronize()
@@ -209,7 +208,8 @@ def main(argv: Optional[List[str]] = None) -> int:
     if args.save or args.resume:
         out = args.resume if (args.resume and not args.save) else args.save
         if out and str(out).lower() == "true":
-            out = escg_io.run_dir_name(run.L, run.S, run.mobility)
+            out = escg_io.run_dir_name(run.L, run.S, run.mobility,
+                                       "moore" if run.moore else "vn")
         os.makedirs(out, exist_ok=True)
         escg_io.write_params_csv(os.path.join(out, "params.csv"),
                                  run.params_record())

@@ -59,8 +59,7 @@ def test_params_csv_round_trip(tmp_path):
                                                "mobility": "3e-05"}
 
 
-@pytest.mark.parametrize("argv", [["--height", "100"], ["--neighbourhood", "8"],
-                                  ["--flux", "false"]])
+@pytest.mark.parametrize("argv", [["--height", "100"], ["--flux", "false"]])
 def test_unsupported_options_refused_before_device_work(argv):
     args = cli.build_parser().parse_args(["--length", "64"] + argv)
     with pytest.raises(SystemExit):

@@ -66,3 +66,18 @@ def test_cli_dominance_import_and_exact_monoculture_stop(tmp_path):
     r = O.o2_run_until(job, ref, 0, 20000, O.MONOCULTURE)
     assert r[0] == 1 and mcs == r[1]
     assert np.array_equal(g, ref)
+
+
+def test_cli_moore_run_and_resume_match_oracle(tmp_path):
+    d = str(tmp_path / "moore")
+    base = ["--length", "48", "--mobility", "1e-4", "--seed", "4",
+            "--printFrequency", "8", "--quiet", "--neighbourhood", "8"]
+    _run(base + ["--mcs", "9", "--save", d])
+    _run(["--resume", d, "--mcs", "20", "--quiet"])
+    g, L, mcs = escg_io.read_grid_csv(d + "/grid.csv")
+    assert (L, mcs) == (48, 20)
+    job = O.Job(48, 3, O.circulant_matrix(3, [1]),
+                eps_from_mobility(1e-4, 48), seed=4, nbhd=8)
+    ref = job.init()
+    O.o2_run(job, ref, 0, 20, want_counts=False)
+    assert np.array_equal(g, ref)
