@@ -16,6 +16,7 @@ import ctypes as C
 import os
 import subprocess
 from dataclasses import dataclass, field
+from typing import Optional
 
 import numpy as np
 
@@ -57,7 +58,7 @@ def lib():
         u32 = C.c_uint32
         dbl = C.c_double
         job = [u32, u32, u8p, dbl, dbl, dbl, C.c_uint64, u32, C.c_int,
-               C.c_int]
+               C.c_int, C.c_void_p]
         L.orc_philox4x32.argtypes = [u32p, u32p, C.c_int, u32p]
         L.orc_circulant_matrix.argtypes = [u32, u32, u8p]
         L.orc_pair_rule.argtypes = [C.c_int, C.c_uint8, C.c_uint8, u32, u8p,
@@ -139,7 +140,9 @@ class Job:
     dominance matrix D (S x S, paper layout), rates by role (exchange =
     migration, selection = interaction, reproduction), the RNG key, and the
     neighbourhood (4-way von Neumann or 8-way Moore, the paper's
-    --neighbourhood option)."""
+    --neighbourhood option) and optional dominance probabilities P (entry
+    (a-1, b-1): probability that a selection of a against b succeeds, used
+    where D says a dominates b; None = deterministic)."""
     L: int
     S: int
     D: np.ndarray
@@ -150,18 +153,27 @@ class Job:
     replica: int = 0
     rounds: int = 10
     nbhd: int = 4          # 4: von Neumann, 8: Moore
+    P: Optional[np.ndarray] = None  # S x S dominance probabilities or None
     _Dflat: np.ndarray = field(init=False, repr=False)
+    _Pflat: Optional[np.ndarray] = field(init=False, repr=False)
 
     def __post_init__(self):
         D = np.ascontiguousarray(self.D, dtype=np.uint8).reshape(-1)
         assert D.size == self.S * self.S
         assert self.nbhd in (4, 8)
+        self._Pflat = None
+        if self.P is not None:
+            P = np.ascontiguousarray(self.P, dtype=np.float64).reshape(-1)
+            assert P.size == self.S * self.S
+            assert ((P >= 0.0) & (P <= 1.0)).all()
+            self._Pflat = P
         self._Dflat = D
 
     def args(self):
         return (self.L, self.S, self._Dflat, float(self.ex), float(self.sel),
                 float(self.rep), int(self.seed), int(self.replica),
-                int(self.rounds), int(self.nbhd))
+                int(self.rounds), int(self.nbhd),
+                None if self._Pflat is None else self._Pflat.ctypes.data)
 
     def init(self) -> np.ndarray:
         return init_lattice(self.L, self.S, self.seed, self.replica,

@@ -154,6 +154,56 @@ void orc_pair_rule(int action, uint8_t x, uint8_t y, uint32_t S,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Probabilistic dominance (the interaction variant the paper adopts to      */
+/* replicate Park, Chen and Szolnoki, Sec. "Extending Current Literature"): */
+/* a directed edge a -> b of the dominance matrix carries a probability      */
+/* P[(a-1)*S + (b-1)] in [0, 1] that a selection between the two succeeds.   */
+/* As in the Dominance Check order, the selected cell's win is tried first   */
+/* (probability P_xy, zero unless x dominates y); only if it fails is the    */
+/* neighbour's win tried (P_yx).  P equal to the 0/1 matrix D gives the      */
+/* deterministic rule.  P == NULL means deterministic.                       */
+/* ------------------------------------------------------------------------ */
+static double win_prob(uint8_t a, uint8_t b, uint32_t S, const uint8_t *D,
+                       const double *P)
+{
+    if (!dominates(a, b, S, D))
+        return 0.0;
+    return P[(uint32_t)(a - 1) * S + (uint32_t)(b - 1)];
+}
+
+/* O1's selection with probabilities: f uniform on [0, 1). */
+static void selection_prob_f(double f, uint8_t *cell, uint8_t *nbr, uint32_t S,
+                             const uint8_t *D, const double *P)
+{
+    uint8_t x = *cell, y = *nbr;
+    if (x == y || x == 0 || y == 0)
+        return;
+    double pxy = win_prob(x, y, S, D, P), pyx = win_prob(y, x, S, D, P);
+    if (f < pxy)
+        *nbr = 0;
+    else if (f < pxy + pyx * (1.0 - pxy))
+        *cell = 0;
+}
+
+/* O2's selection with probabilities: v uniform on {0, ..., R-1}, R = T2 - T1
+ * (the selection draw u minus T1).  x wins if v < A, else y wins if v < B,
+ * with A = floor(P_xy R) and B = A + floor(P_yx (R - A)), in double. */
+static void selection_prob_v(uint32_t v, uint32_t R, uint8_t *cell,
+                             uint8_t *nbr, uint32_t S, const uint8_t *D,
+                             const double *P)
+{
+    uint8_t x = *cell, y = *nbr;
+    if (x == y || x == 0 || y == 0)
+        return;
+    uint32_t A = (uint32_t)floor(win_prob(x, y, S, D, P) * (double)R);
+    uint32_t B = A + (uint32_t)floor(win_prob(y, x, S, D, P) * (double)(R - A));
+    if (v < A)
+        *nbr = 0;
+    else if (v < B)
+        *cell = 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Action thresholds.  The paper draws r uniform on [0, mu+sigma+eps] and    */
 /* picks migration if r < eps, interaction if r < eps + mu, else            */
 /* reproduction (Algorithm "Elementary Step"; rates normalised to a roulette */
@@ -245,7 +295,8 @@ typedef struct {
     uint64_t seed;
     uint32_t replica;
     int rounds;
-    int nbhd; /* 4 (von Neumann) or 8 (Moore) */
+    int nbhd;        /* 4 (von Neumann) or 8 (Moore) */
+    const double *P; /* dominance probabilities or NULL (deterministic) */
 } o2_job;
 
 static void o2_pass(const o2_job *j, uint32_t t, uint32_t p, uint8_t *grid)
@@ -279,8 +330,12 @@ static void o2_pass(const o2_job *j, uint32_t t, uint32_t p, uint8_t *grid)
                 cell = second;
                 nbr = first;
             }
-            pair_rule(action_of(w >> 8, j->T1, j->T2), &grid[cell], &grid[nbr],
-                      j->S, j->D);
+            int action = action_of(w >> 8, j->T1, j->T2);
+            if (j->P && action == ACT_SELECTION)
+                selection_prob_v((w >> 8) - j->T1, j->T2 - j->T1, &grid[cell],
+                                 &grid[nbr], j->S, j->D, j->P);
+            else
+                pair_rule(action, &grid[cell], &grid[nbr], j->S, j->D);
         }
     }
 }
@@ -293,11 +348,11 @@ static void o2_mcs(const o2_job *j, uint32_t t, uint8_t *grid)
 
 static o2_job make_job(uint32_t L, uint32_t S, const uint8_t *D, double ex,
                        double sel, double rep, uint64_t seed, uint32_t replica,
-                       int rounds, int nbhd)
+                       int rounds, int nbhd, const double *P)
 {
     o2_job j;
     j.L = L; j.S = S; j.D = D; j.seed = seed; j.replica = replica;
-    j.rounds = rounds; j.nbhd = nbhd;
+    j.rounds = rounds; j.nbhd = nbhd; j.P = P;
     orc_thresholds(ex, sel, rep, &j.T1, &j.T2);
     return j;
 }
@@ -305,10 +360,10 @@ static o2_job make_job(uint32_t L, uint32_t S, const uint8_t *D, double ex,
 /* One pass only, for the one-pass distribution tests. */
 void orc_o2_pass(uint32_t L, uint32_t S, const uint8_t *D, double ex,
                  double sel, double rep, uint64_t seed, uint32_t replica,
-                 int rounds, int nbhd, uint32_t t, uint32_t p,
-                 uint8_t *grid)
+                 int rounds, int nbhd, const double *P, uint32_t t,
+                 uint32_t p, uint8_t *grid)
 {
-    o2_job j = make_job(L, S, D, ex, sel, rep, seed, replica, rounds, nbhd);
+    o2_job j = make_job(L, S, D, ex, sel, rep, seed, replica, rounds, nbhd, P);
     o2_pass(&j, t, p, grid);
 }
 
@@ -318,10 +373,10 @@ void orc_o2_pass(uint32_t L, uint32_t S, const uint8_t *D, double ex,
  * each MCS and once more at the end. */
 void orc_o2_run(uint32_t L, uint32_t S, const uint8_t *D, double ex,
                 double sel, double rep, uint64_t seed, uint32_t replica,
-                int rounds, int nbhd, uint32_t mcs0, uint32_t n_mcs,
-                uint8_t *grid, uint32_t *counts)
+                int rounds, int nbhd, const double *P, uint32_t mcs0,
+                uint32_t n_mcs, uint8_t *grid, uint32_t *counts)
 {
-    o2_job j = make_job(L, S, D, ex, sel, rep, seed, replica, rounds, nbhd);
+    o2_job j = make_job(L, S, D, ex, sel, rep, seed, replica, rounds, nbhd, P);
     if (counts)
         orc_counts(L, S, grid, counts);
     for (uint32_t k = 0; k < n_mcs; ++k) {
@@ -354,10 +409,11 @@ static int stop_met(uint32_t S, const uint32_t *c, int mode)
  * t_ext. */
 void orc_o2_run_until(uint32_t L, uint32_t S, const uint8_t *D, double ex,
                       double sel, double rep, uint64_t seed, uint32_t replica,
-                      int rounds, int nbhd, uint32_t mcs0, uint32_t max_mcs,
-                      int mode, uint8_t *grid, uint32_t *result)
+                      int rounds, int nbhd, const double *P, uint32_t mcs0,
+                      uint32_t max_mcs, int mode, uint8_t *grid,
+                      uint32_t *result)
 {
-    o2_job j = make_job(L, S, D, ex, sel, rep, seed, replica, rounds, nbhd);
+    o2_job j = make_job(L, S, D, ex, sel, rep, seed, replica, rounds, nbhd, P);
     uint32_t *c = result + 2;
     uint32_t t = 0;
     orc_counts(L, S, grid, c);
@@ -385,7 +441,8 @@ void orc_o2_run_until(uint32_t L, uint32_t S, const uint8_t *D, double ex,
 /* ------------------------------------------------------------------------ */
 static void o1_step(uint32_t L, uint32_t S, const uint8_t *D, double ex,
                     double sel, double tot, uint64_t seed, uint32_t replica,
-                    int rounds, int nbhd, uint64_t k, uint8_t *grid)
+                    int rounds, int nbhd, const double *P, uint64_t k,
+                    uint8_t *grid)
 {
     uint32_t ctr[4] = {(uint32_t)k, (uint32_t)(k >> 32), TAG_RSU << 8, replica};
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
@@ -417,13 +474,16 @@ static void o1_step(uint32_t L, uint32_t S, const uint8_t *D, double ex,
         action = ACT_SELECTION;
     else
         action = ACT_REPRODUCE;
-    pair_rule(action, &grid[i], &grid[ni], S, D);
+    if (P && action == ACT_SELECTION)
+        selection_prob_f((r - ex) / sel, &grid[i], &grid[ni], S, D, P);
+    else
+        pair_rule(action, &grid[i], &grid[ni], S, D);
 }
 
 void orc_o1_run(uint32_t L, uint32_t S, const uint8_t *D, double ex,
                 double sel, double rep, uint64_t seed, uint32_t replica,
-                int rounds, int nbhd, uint32_t mcs0, uint32_t n_mcs,
-                uint8_t *grid, uint32_t *counts)
+                int rounds, int nbhd, const double *P, uint32_t mcs0,
+                uint32_t n_mcs, uint8_t *grid, uint32_t *counts)
 {
     uint64_t N = (uint64_t)L * L;
     double tot = (ex + sel) + rep;
@@ -432,8 +492,8 @@ void orc_o1_run(uint32_t L, uint32_t S, const uint8_t *D, double ex,
     for (uint32_t m = 0; m < n_mcs; ++m) {
         uint64_t k0 = (uint64_t)(mcs0 + m) * N;
         for (uint64_t n = 0; n < N; ++n)
-            o1_step(L, S, D, ex, sel, tot, seed, replica, rounds, nbhd, k0 + n,
-                    grid);
+            o1_step(L, S, D, ex, sel, tot, seed, replica, rounds, nbhd, P,
+                    k0 + n, grid);
         if (counts)
             orc_counts(L, S, grid, counts + (size_t)(m + 1) * (S + 1));
     }
@@ -443,19 +503,20 @@ void orc_o1_run(uint32_t L, uint32_t S, const uint8_t *D, double ex,
  * k0 .. k0 + n - 1 of the O1 stream. */
 void orc_o1_steps(uint32_t L, uint32_t S, const uint8_t *D, double ex,
                   double sel, double rep, uint64_t seed, uint32_t replica,
-                  int rounds, int nbhd, uint64_t k0, uint64_t n,
-                  uint8_t *grid)
+                  int rounds, int nbhd, const double *P, uint64_t k0,
+                  uint64_t n, uint8_t *grid)
 {
     double tot = (ex + sel) + rep;
     for (uint64_t k = 0; k < n; ++k)
-        o1_step(L, S, D, ex, sel, tot, seed, replica, rounds, nbhd, k0 + k,
+        o1_step(L, S, D, ex, sel, tot, seed, replica, rounds, nbhd, P, k0 + k,
                 grid);
 }
 
 void orc_o1_run_until(uint32_t L, uint32_t S, const uint8_t *D, double ex,
                       double sel, double rep, uint64_t seed, uint32_t replica,
-                      int rounds, int nbhd, uint32_t mcs0, uint32_t max_mcs,
-                      int mode, uint8_t *grid, uint32_t *result)
+                      int rounds, int nbhd, const double *P, uint32_t mcs0,
+                      uint32_t max_mcs, int mode, uint8_t *grid,
+                      uint32_t *result)
 {
     uint64_t N = (uint64_t)L * L;
     double tot = (ex + sel) + rep;
@@ -466,8 +527,8 @@ void orc_o1_run_until(uint32_t L, uint32_t S, const uint8_t *D, double ex,
     while (!met && t < max_mcs) {
         uint64_t k0 = (uint64_t)(mcs0 + t) * N;
         for (uint64_t n = 0; n < N; ++n)
-            o1_step(L, S, D, ex, sel, tot, seed, replica, rounds, nbhd, k0 + n,
-                    grid);
+            o1_step(L, S, D, ex, sel, tot, seed, replica, rounds, nbhd, P,
+                    k0 + n, grid);
         t++;
         orc_counts(L, S, grid, c);
         met = stop_met(S, c, mode);

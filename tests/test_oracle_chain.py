@@ -19,6 +19,9 @@ streams (replica ids) and compared by a G-test.
 * The same three pins for the 8-way Moore neighbourhood (the paper's
   --neighbourhood 8), whose random-sequential step picks one of eight
   neighbours.
+* Probabilistic dominance: the L = 2 chains and the L = 4 one-pass law with
+  win probabilities on a mutual matrix, and the exact reductions P = D
+  (deterministic) and P = 0 (no selection).
 """
 import itertools
 
@@ -60,7 +63,20 @@ def neighbours(r, c, L, nbhd):
     return [((r + dr) % L, (c + dc) % L) for dr, dc in d]
 
 
-def rsu_step_dist(L, S, D, rates, dist, nbhd=4):
+def outcomes(a, x, y, D, P):
+    """[(x', y'), prob] of one action on the pair (selected x, neighbour y):
+    the prose rule, except that with dominance probabilities P a selection
+    tries the selected cell's win first (probability P[x][y] where x
+    dominates y) and then the neighbour's (P[y][x] where y dominates x)."""
+    if P is None or a != O.SELECTION or x == y or x == 0 or y == 0:
+        return [(_prose_rule(a, x, y, D), 1.0)]
+    pxy = P[x - 1, y - 1] if D[x - 1, y - 1] else 0.0
+    pyx = P[y - 1, x - 1] if D[y - 1, x - 1] else 0.0
+    return [((x, 0), pxy), ((0, y), (1 - pxy) * pyx),
+            ((x, y), (1 - pxy) * (1 - pyx))]
+
+
+def rsu_step_dist(L, S, D, rates, dist, nbhd=4, P=None):
     """One random-sequential step applied to a distribution over lattices
     (dict tuple -> prob): a uniform cell, a uniform one of its nbhd
     neighbours (direction chosen uniformly, wrap), an action by rate."""
@@ -78,10 +94,11 @@ def rsu_step_dist(L, S, D, rates, dist, nbhd=4):
                 for a, q in pa.items():
                     if q == 0.0:
                         continue
-                    s = list(state)
-                    s[i], s[j] = _prose_rule(a, s[i], s[j], D)
-                    t = tuple(s)
-                    out[t] = out.get(t, 0.0) + p * q / (nbhd * N)
+                    for (xn, yn), qo in outcomes(a, state[i], state[j], D, P):
+                        s = list(state)
+                        s[i], s[j] = xn, yn
+                        t = tuple(s)
+                        out[t] = out.get(t, 0.0) + p * q * qo / (nbhd * N)
     return out
 
 
@@ -157,7 +174,7 @@ def test_L3_rsu_matches_exact_chain():
     assert g_test(sample(run, n), dist, n) > 1e-4
 
 
-def block_pass_dist(L, S, D, rates, g0, nbhd=4):
+def block_pass_dist(L, S, D, rates, g0, nbhd=4, P=None):
     """Exact law of one O2 pass from g0: offsets uniform on {0,1}^2; the
     (L/2)^2 disjoint 2x2 blocks update independently, each on one of its
     internal pairs with a uniform orientation and an action drawn with
@@ -178,7 +195,7 @@ def block_pass_dist(L, S, D, rates, g0, nbhd=4):
             A, B, C_, Dd = (r0 * L + c0, r0 * L + c1, r1 * L + c0,
                             r1 * L + c1)
             sites = (A, B, C_, Dd)
-            outcomes = {}
+            res = {}
             pairs = [((A, B), 1), ((C_, Dd), 1), ((A, C_), 1), ((B, Dd), 1)]
             if nbhd == 8:
                 pairs += [((A, Dd), 2), ((B, C_), 2)]
@@ -186,18 +203,19 @@ def block_pass_dist(L, S, D, rates, g0, nbhd=4):
             for (f, s), wt in pairs:
                 for cell, nbr in ((f, s), (s, f)):
                     for a, q in pa:
-                        loc = {k: int(g0[k]) for k in sites}
-                        loc[cell], loc[nbr] = _prose_rule(a, loc[cell],
-                                                          loc[nbr], D)
-                        key = tuple(loc[k] for k in sites)
-                        outcomes[key] = (outcomes.get(key, 0.0) +
-                                         q * wt / (2 * wsum))
-            per_block.append((sites, outcomes))
+                        for (xn, yn), qo in outcomes(a, int(g0[cell]),
+                                                     int(g0[nbr]), D, P):
+                            loc = {k: int(g0[k]) for k in sites}
+                            loc[cell], loc[nbr] = xn, yn
+                            key = tuple(loc[k] for k in sites)
+                            res[key] = (res.get(key, 0.0) +
+                                        q * qo * wt / (2 * wsum))
+            per_block.append((sites, res))
         joint = {tuple(g0.tolist()): 1.0}
-        for sites, outcomes in per_block:
+        for sites, res in per_block:
             nxt = {}
             for st, p in joint.items():
-                for vals, q in outcomes.items():
+                for vals, q in res.items():
                     s = list(st)
                     for k, v in zip(sites, vals):
                         s[k] = v
@@ -334,6 +352,90 @@ def test_moore_law_differs_from_von_neumann():
     obs = sample(run, n)
     vn = {k: vn.get(k, 0.0) + 1e-12 for k in set(vn) | set(obs)}
     assert g_test(obs, vn, n) < 1e-6
+
+
+# --- Probabilistic dominance -----------------------------------------------
+# Dominance probabilities on a mutual matrix (1 and 2 beat each other, 3
+# beats 1), so both orders of the two win tests matter.
+P_MUTUAL = np.array([[0.0, 0.35, 0.0], [0.6, 0.0, 0.0], [0.25, 0.0, 0.0]])
+
+
+@pytest.mark.parametrize("nbhd", [4, 8])
+def test_L2_probabilistic_rsu_matches_exact_chain(nbhd):
+    L, S = 2, 3
+    rates = (0.5, 2.0, 1.0)
+    g0 = np.array([1, 2, 0, 3], np.uint8)
+    dist = {tuple(g0.tolist()): 1.0}
+    for _ in range(4):
+        dist = rsu_step_dist(L, S, D_MUTUAL, rates, dist, nbhd=nbhd,
+                             P=P_MUTUAL)
+    n = 20000
+
+    def run(rep):
+        job = O.Job(L, S, D_MUTUAL, *rates, seed=21, replica=rep, nbhd=nbhd,
+                    P=P_MUTUAL)
+        g = g0.copy()
+        O.o1_steps(job, g, 0, 4)
+        return g
+    assert g_test(sample(run, n), dist, n) > 1e-4
+
+
+@pytest.mark.parametrize("nbhd", [4, 8])
+def test_L2_probabilistic_block_schedule_mcs_equals_four_rsu_steps(nbhd):
+    # O2 quantises each probability to multiples of 1 / (T2 - T1) ~ 2^-23:
+    # far below what 20000 samples resolve
+    L, S = 2, 3
+    rates = (0.5, 2.0, 1.0)
+    g0 = np.array([3, 1, 2, 1], np.uint8)
+    dist = {tuple(g0.tolist()): 1.0}
+    for _ in range(4):
+        dist = rsu_step_dist(L, S, D_MUTUAL, rates, dist, nbhd=nbhd,
+                             P=P_MUTUAL)
+    n = 20000
+
+    def run(rep):
+        job = O.Job(L, S, D_MUTUAL, *rates, seed=8, replica=rep, nbhd=nbhd,
+                    P=P_MUTUAL)
+        g = g0.copy()
+        O.o2_run(job, g, 2, 1, want_counts=False)
+        return g
+    assert g_test(sample(run, n), dist, n) > 1e-4
+
+
+def test_L4_probabilistic_one_pass_matches_exact_block_law():
+    L, S = 4, 3
+    rates = (0.5, 2.0, 1.0)
+    g0 = np.array([1, 2, 0, 3, 3, 3, 1, 0, 0, 2, 2, 1, 1, 0, 3, 2], np.uint8)
+    dist = block_pass_dist(L, S, D_MUTUAL, rates, g0, P=P_MUTUAL)
+    assert abs(sum(dist.values()) - 1.0) < 1e-9
+    n = 40000
+
+    def run(rep):
+        job = O.Job(L, S, D_MUTUAL, *rates, seed=12, replica=rep, P=P_MUTUAL)
+        g = g0.copy()
+        O.o2_pass(job, g, 3, rep % 4)
+        return g
+    assert g_test(sample(run, n), dist, n) > 1e-4
+
+
+@pytest.mark.parametrize("runner", ["o1", "o2"])
+@pytest.mark.parametrize("nbhd", [4, 8])
+def test_probabilities_equal_to_the_matrix_give_the_deterministic_rule(
+        runner, nbhd):
+    # P = D: every permitted win succeeds, the rule is the deterministic
+    # one, run for run; P = 0 removes all selection, as D = 0 does
+    L, S = 12, 5
+    D = O.circulant_matrix(S, [1, 3])
+    D[0, 1] = 0
+    run = O.o1_run if runner == "o1" else O.o2_run
+    g0 = np.random.default_rng(3).integers(0, S + 1, L * L, dtype=np.uint8)
+    for P, Dref in ((D.astype(np.float64), D),
+                    (np.zeros((S, S)), np.zeros((S, S), np.uint8))):
+        a, b = g0.copy(), g0.copy()
+        ca = run(O.Job(L, S, D, 0.7, 1.3, 1.0, seed=4, nbhd=nbhd, P=P), a,
+                 3, 6)
+        cb = run(O.Job(L, S, Dref, 0.7, 1.3, 1.0, seed=4, nbhd=nbhd), b, 3, 6)
+        assert np.array_equal(a, b) and np.array_equal(ca, cb)
 
 
 def test_g_test_detects_a_planted_rule_error():
