@@ -82,7 +82,21 @@ typedef struct escg_params {
     uint64_t seed;     /* Philox key                                        */
     uint32_t replica;  /* independent stream id under the same seed         */
     uint32_t flags;    /* ESCG_FLAG_*; other bits must be 0                 */
+    const double *dom_prob; /* NULL, or S*S dominance probabilities (host)  */
 } escg_params;
+
+/* dom_prob: probabilistic dominance, the interaction variant the paper uses
+ * to replicate Park, Chen and Szolnoki (Sec. "Extending Current
+ * Literature"): entry (a-1)*S + (b-1), in [0, 1], is the probability that a
+ * selection of species a against species b succeeds where dom[a] has bit b
+ * (entries elsewhere are ignored).  The selected cell's win is tried first,
+ * then the neighbour's, as in the Dominance Check.  A selection draw u
+ * (T1 <= u < T2) decides both: with R = T2 - T1 and, in double,
+ * A = floor(P_xy R), B = A + floor(P_yx (R - A)), the selected cell x wins
+ * if u - T1 < A, else the neighbour y wins if u - T1 < B, else nothing
+ * happens.  dom_prob equal to the 0/1 matrix gives the deterministic rule
+ * bit for bit.  Read during the call only.  EINVAL if an entry is not in
+ * [0, 1]. */
 
 /* flags: the 8-way Moore neighbourhood instead of the 4-way von Neumann one
  * (the paper's --neighbourhood option, Sec. "Single Threaded ESCG in C++").

@@ -52,6 +52,7 @@ struct JobDev {
     uint32_t L, S, T1, T2;
     uint32_t replica, mcs0, max_mcs, mode;
     uint32_t init, result_words, moore, pad1;
+    const uint32_t *ab;   // selection thresholds (dominance probabilities)
     uint32_t dom[32];
 };
 
@@ -116,7 +117,7 @@ __device__ __forceinline__ void count_dwords(const uint32_t *lat32,
     }
 }
 
-template <bool kPacked>
+template <bool kPacked, bool kProb>
 __device__ void run_job_lds(const JobDev &J, uint8_t *base, uint8_t *smem,
                             LdsTables<kPacked ? 8 : 32> &TB)
 {
@@ -128,7 +129,7 @@ __device__ void run_job_lds(const JobDev &J, uint8_t *base, uint8_t *smem,
     const uint32_t k0 = (uint32_t)J.seed, k1 = (uint32_t)(J.seed >> 32);
     uint8_t *g = base + J.lat_off;
 
-    setup_tables(TB, J.dom, J.moore != 0);
+    setup_tables(TB, J.dom, J.moore != 0, kProb ? J.ab : nullptr);
     // row padding bytes match no species
     if (LS != L)
         for (uint32_t r = tid; r < L; r += nt)
@@ -161,7 +162,7 @@ __device__ void run_job_lds(const JobDev &J, uint8_t *base, uint8_t *smem,
         }
     }
     __syncthreads();
-    const QuadCtx qc = make_quad_ctx(TB, J.T1, J.T2);
+    const auto qc = make_quad_ctx<kProb>(TB, J.T1, J.T2);
     const LdsWalk W = lds_walk(L, LS);
     const uint32_t ndw = (LS * L) >> 2;
 
@@ -221,16 +222,16 @@ __device__ void run_job_lds(const JobDev &J, uint8_t *base, uint8_t *smem,
     __syncthreads();
 }
 
-template <bool kPacked>
+template <bool kPacked, bool kProb>
 __global__ __launch_bounds__(512) void lds_single_kernel(JobDev J,
                                                          uint8_t *base)
 {
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ LdsTables<kPacked ? 8 : 32> TB;
-    run_job_lds<kPacked>(J, base, smem, TB);
+    run_job_lds<kPacked, kProb>(J, base, smem, TB);
 }
 
-template <bool kPacked>
+template <bool kPacked, bool kProb>
 __global__ __launch_bounds__(512) void lds_batch_kernel(
     const JobDev *__restrict__ jobs, const uint32_t *__restrict__ order,
     uint32_t n, uint32_t *queue, uint8_t *base)
@@ -245,7 +246,7 @@ __global__ __launch_bounds__(512) void lds_batch_kernel(
         __syncthreads();
         if (qi >= n)
             return;
-        run_job_lds<kPacked>(jobs[order[qi]], base, smem, TB);
+        run_job_lds<kPacked, kProb>(jobs[order[qi]], base, smem, TB);
     }
 }
 
@@ -265,6 +266,7 @@ struct TileArgs {
     const uint32_t *done; // non-null and nonzero: only copy src to dst
     uint64_t seed;
     uint64_t dom_packed;
+    const uint32_t *ab;   // selection thresholds (global) or null
     uint32_t L, S, T1, T2, replica, t, moore;
     uint32_t dom[32];
 };
@@ -362,10 +364,10 @@ __global__ __launch_bounds__(kTileThreads) void tile_mcs_kernel(TileArgs a)
                     const uint32_t pA = lr * LS + lc;
                     if (kPacked)
                         update_block(lat, pA, pA + 1, pA + LS, pA + LS + 1, w,
-                                     a.T1, a.T2, dp, a.moore != 0);
+                                     a.T1, a.T2, dp, a.moore != 0, a.ab, 8u);
                     else
                         update_block(lat, pA, pA + 1, pA + LS, pA + LS + 1, w,
-                                     a.T1, a.T2, dt, a.moore != 0);
+                                     a.T1, a.T2, dt, a.moore != 0, a.ab, 32u);
                 }
             }
         }
@@ -438,10 +440,11 @@ struct TiledArgs {
     uint64_t seed;
     TileGeom G;
     uint32_t S, T1, T2, replica, mcs0, n_mcs, spin_limit, moore;
+    const uint32_t *ab;   // selection thresholds (global) or null
     uint32_t dom[32];
 };
 
-template <bool kPacked>
+template <bool kPacked, bool kProb>
 __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
 {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -463,8 +466,8 @@ __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
     if (tid == 0)
         s_misc[0] = 0;
     tile_load(lat, a.lattice, G, ty, tx);
-    setup_tables(TB, a.dom, a.moore != 0); // ends with a barrier
-    const QuadCtx qc = make_quad_ctx(TB, a.T1, a.T2);
+    setup_tables(TB, a.dom, a.moore != 0, kProb ? a.ab : nullptr);
+    const auto qc = make_quad_ctx<kProb>(TB, a.T1, a.T2); // after a barrier
     const TileWalk W = tile_walk(G, ty, tx);
 
     bool aborted = false;
@@ -518,10 +521,11 @@ struct StepArgs {
     uint64_t seed;
     TileGeom G;
     uint32_t S, T1, T2, replica, t, moore;
+    const uint32_t *ab;   // selection thresholds (global) or null
     uint32_t dom[32];
 };
 
-template <bool kPacked>
+template <bool kPacked, bool kProb>
 __global__ __launch_bounds__(512) void tiled_step_kernel(StepArgs a)
 {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -542,8 +546,8 @@ __global__ __launch_bounds__(512) void tiled_step_kernel(StepArgs a)
         return;
     }
     tile_load(lat, a.src, G, ty, tx);
-    setup_tables(TB, a.dom, a.moore != 0);
-    const QuadCtx qc = make_quad_ctx(TB, a.T1, a.T2);
+    setup_tables(TB, a.dom, a.moore != 0, kProb ? a.ab : nullptr);
+    const auto qc = make_quad_ctx<kProb>(TB, a.T1, a.T2);
     tile_mcs(lat, G, tile_walk(G, ty, tx), a.t, a.replica, (uint32_t)a.seed,
              (uint32_t)(a.seed >> 32), qc);
     tile_store(lat, a.dst, G, ty, tx);
@@ -569,12 +573,13 @@ struct BatchStepJob {
     TileGeom G;
     uint32_t S, T1, T2, replica, t0;
     uint32_t wg0, moore;
+    const uint32_t *ab;   // selection thresholds (global) or null
     uint32_t dom[32];
 };
 
 constexpr uint32_t kBatchStepThreads = 512;
 
-template <bool kPacked>
+template <bool kPacked, bool kProb>
 __global__ __launch_bounds__(kBatchStepThreads) void tiled_step_batch_kernel(
     const BatchStepJob *jobs, uint32_t njobs, uint32_t k)
 {
@@ -597,8 +602,8 @@ __global__ __launch_bounds__(kBatchStepThreads) void tiled_step_batch_kernel(
     uint8_t *dst = (k & 1u) ? J.lattice : J.scratch;
     uint8_t *lat = smem;
     tile_load(lat, src, G, ty, tx);
-    setup_tables(TB, J.dom, J.moore != 0);
-    const QuadCtx qc = make_quad_ctx(TB, J.T1, J.T2);
+    setup_tables(TB, J.dom, J.moore != 0, kProb ? J.ab : nullptr);
+    const auto qc = make_quad_ctx<kProb>(TB, J.T1, J.T2);
     tile_mcs(lat, G, tile_walk(G, ty, tx), J.t0 + k, J.replica,
              (uint32_t)J.seed, (uint32_t)(J.seed >> 32), qc);
     tile_store(lat, dst, G, ty, tx);
@@ -712,7 +717,68 @@ struct Derived {
     uint32_t T1, T2;
     uint64_t packed;
     bool small; // S <= 7: packed dominance
+    bool prob;  // dominance probabilities: selection thresholds in `ab`
+    std::vector<uint32_t> ab;      // A then B tables, Sp * Sp u32 each
+    const uint32_t *d_ab = nullptr; // `ab` on the device (set by the caller)
 };
+
+// Selection thresholds of a job with dominance probabilities (P = the 0/1
+// matrix when `p` has none, which reproduces the deterministic rule): for
+// x != y in 1..S, with R = T2 - T1 and in double, A = floor(P_xy R) and
+// B = A + floor(P_yx (R - A)), P_xy counting only where x dominates y.
+// Table stride Sp = 8 (S <= 7) or 32.
+std::vector<uint32_t> selection_thresholds(const escg_params *p, uint32_t T1,
+                                           uint32_t T2, uint32_t Sp = 0)
+{
+    const uint32_t S = p->S, R = T2 - T1;
+    if (Sp == 0)
+        Sp = S <= 7 ? 8u : 32u;
+    std::vector<uint32_t> ab(2u * Sp * Sp, 0u);
+    auto prob = [&](uint32_t a, uint32_t b) {
+        if (!((p->dom[a] >> b) & 1u))
+            return 0.0;
+        return p->dom_prob ? p->dom_prob[(a - 1) * S + (b - 1)] : 1.0;
+    };
+    for (uint32_t x = 1; x <= S; ++x)
+        for (uint32_t y = 1; y <= S; ++y) {
+            if (x == y)
+                continue;
+            const uint32_t A = (uint32_t)std::floor(prob(x, y) * (double)R);
+            const uint32_t B =
+                A + (uint32_t)std::floor(prob(y, x) * (double)(R - A));
+            ab[x * Sp + y] = A;
+            ab[Sp * Sp + x * Sp + y] = B;
+        }
+    return ab;
+}
+
+// Device scratch released stream-ordered when it goes out of scope (after
+// every launch that the scope enqueued).
+struct StreamBuf {
+    hipStream_t st;
+    void *ptr = nullptr;
+    explicit StreamBuf(hipStream_t s) : st(s) {}
+    ~StreamBuf()
+    {
+        if (ptr)
+            (void)hipFreeAsync(ptr, st);
+    }
+    StreamBuf(const StreamBuf &) = delete;
+    StreamBuf &operator=(const StreamBuf &) = delete;
+};
+
+// Copies host words to new stream-ordered device memory held by `buf`.
+escg_status upload_words(const std::vector<uint32_t> &h, StreamBuf &buf)
+{
+    if (hipMallocAsync(&buf.ptr, h.size() * 4, buf.st) != hipSuccess) {
+        buf.ptr = nullptr;
+        return ESCG_ENOMEM;
+    }
+    if (hipMemcpyAsync(buf.ptr, h.data(), h.size() * 4, hipMemcpyHostToDevice,
+                       buf.st) != hipSuccess)
+        return ESCG_EDEVICE;
+    return ESCG_OK;
+}
 
 escg_status validate(const escg_params *p)
 {
@@ -724,6 +790,10 @@ escg_status validate(const escg_params *p)
         return ESCG_EINVAL;
     if (p->flags & ~ESCG_FLAG_MOORE)
         return ESCG_EINVAL;
+    if (p->dom_prob)
+        for (uint32_t i = 0; i < p->S * p->S; ++i)
+            if (!(p->dom_prob[i] >= 0.0 && p->dom_prob[i] <= 1.0))
+                return ESCG_EINVAL;
     const double r[3] = {p->rate_ex, p->rate_sel, p->rate_rep};
     for (double v : r)
         if (!(v >= 0.0) || !std::isfinite(v))
@@ -748,6 +818,9 @@ Derived derive(const escg_params *p)
     Derived d;
     escg_thresholds(p, &d.T1, &d.T2);
     d.small = p->S <= 7;
+    d.prob = p->dom_prob != nullptr;
+    if (d.prob)
+        d.ab = selection_thresholds(p, d.T1, d.T2);
     d.packed = 0;
     if (d.small)
         for (uint32_t a = 1; a <= p->S; ++a)
@@ -855,6 +928,7 @@ JobDev make_job(const escg_params *p, const Derived &d, uint64_t off,
     J.init = init;
     J.result_words = result_words;
     J.moore = (p->flags & ESCG_FLAG_MOORE) ? 1u : 0u;
+    J.ab = d.d_ab;
     for (int i = 0; i < 32; ++i)
         J.dom[i] = p->dom[i];
     return J;
@@ -862,21 +936,23 @@ JobDev make_job(const escg_params *p, const Derived &d, uint64_t off,
 
 uint32_t lds_threads(uint32_t Lmax) { return Lmax <= 128 ? 256u : 512u; }
 
+// The instantiation of a kernel template <bool kPacked, bool kProb>.
+#define ESCG_KERNEL2(K, packed, prob)                                         \
+    ((packed) ? ((prob) ? (const void *)K<true, true>                         \
+                        : (const void *)K<true, false>)                       \
+              : ((prob) ? (const void *)K<false, true>                        \
+                        : (const void *)K<false, false>))
+
 escg_status launch_lds_single(const JobDev &J, bool small, uint8_t *base,
                               hipStream_t st)
 {
     const size_t lds = lds_job_bytes(J.L, J.S);
     const uint32_t nt = lds_threads(J.L);
-    if (small) {
-        allow_dynamic_lds((const void *)lds_single_kernel<true>, lds);
-        hipLaunchKernelGGL(lds_single_kernel<true>, dim3(1), dim3(nt), lds, st,
-                           J, base);
-    } else {
-        allow_dynamic_lds((const void *)lds_single_kernel<false>, lds);
-        hipLaunchKernelGGL(lds_single_kernel<false>, dim3(1), dim3(nt), lds,
-                           st, J, base);
-    }
-    return last_hip(hipGetLastError());
+    const void *fn = ESCG_KERNEL2(lds_single_kernel, small, J.ab != nullptr);
+    allow_dynamic_lds(fn, lds);
+    JobDev j = J;
+    void *args[] = {&j, &base};
+    return last_hip(hipLaunchKernel(fn, dim3(1), dim3(nt), args, lds, st));
 }
 
 escg_status launch_densities(const uint8_t *lat, uint32_t N, uint32_t S,
@@ -925,6 +1001,7 @@ TileArgs tile_args(const escg_params *p, const Derived &d)
     a.T2 = d.T2;
     a.replica = p->replica;
     a.moore = (p->flags & ESCG_FLAG_MOORE) ? 1u : 0u;
+    a.ab = d.d_ab;
     for (int i = 0; i < 32; ++i)
         a.dom[i] = p->dom[i];
     return a;
@@ -1011,8 +1088,8 @@ TiledPlan plan_tiled_uncached(uint32_t L, uint32_t S)
             const uint32_t nt = tiled_threads(G, 1024);
             if (nt == 0)
                 continue;
-            const void *fn = S <= 7 ? (const void *)tiled_persistent_kernel<true>
-                                    : (const void *)tiled_persistent_kernel<false>;
+            const void *fn =
+                ESCG_KERNEL2(tiled_persistent_kernel, S <= 7, false);
             allow_dynamic_lds(fn, lds);
             int per_cu = 0;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nt,
@@ -1137,6 +1214,7 @@ StepArgs step_args(const escg_params *p, const Derived &d,
     a.T2 = d.T2;
     a.replica = p->replica;
     a.moore = (p->flags & ESCG_FLAG_MOORE) ? 1u : 0u;
+    a.ab = d.d_ab;
     for (int i = 0; i < 32; ++i)
         a.dom[i] = p->dom[i];
     return a;
@@ -1146,15 +1224,11 @@ void launch_step(const StepArgs &a, const TiledPlan &sp, bool small,
                  hipStream_t st)
 {
     const uint32_t T = sp.G.TY * sp.G.TX;
-    const void *fn = small ? (const void *)tiled_step_kernel<true>
-                           : (const void *)tiled_step_kernel<false>;
+    const void *fn = ESCG_KERNEL2(tiled_step_kernel, small, a.ab != nullptr);
     allow_dynamic_lds(fn, sp.lds);
-    if (small)
-        hipLaunchKernelGGL(tiled_step_kernel<true>, dim3(T), dim3(sp.threads),
-                           sp.lds, st, a);
-    else
-        hipLaunchKernelGGL(tiled_step_kernel<false>, dim3(T),
-                           dim3(sp.threads), sp.lds, st, a);
+    StepArgs aa = a;
+    void *args[] = {&aa};
+    (void)hipLaunchKernel(fn, dim3(T), dim3(sp.threads), args, sp.lds, st);
 }
 
 // Runs n_mcs MCS of a large lattice with the persistent kernel.  Returns
@@ -1191,6 +1265,7 @@ escg_status run_tiled_persistent(const escg_params *p, const Derived &d,
     a.n_mcs = n_mcs;
     a.spin_limit = 1u << 22; // polls (seconds), then abort with an error
     a.moore = (p->flags & ESCG_FLAG_MOORE) ? 1u : 0u;
+    a.ab = d.d_ab;
     for (int i = 0; i < 32; ++i)
         a.dom[i] = p->dom[i];
     // slot 0 tagged 0, slot 1 tagged 1: neither matches its first use
@@ -1200,8 +1275,7 @@ escg_status run_tiled_persistent(const escg_params *p, const Derived &d,
     if (counts)
         launch_fill(counts + (p->S + 1), (size_t)n_mcs * (p->S + 1), 0, st);
     void *args[] = {&a};
-    const void *fn = d.small ? (const void *)tiled_persistent_kernel<true>
-                             : (const void *)tiled_persistent_kernel<false>;
+    const void *fn = ESCG_KERNEL2(tiled_persistent_kernel, d.small, d.prob);
     allow_dynamic_lds(fn, plan.lds);
     hipError_t e = hipLaunchCooperativeKernel(fn, dim3(T), dim3(plan.threads),
                                               args, (unsigned)plan.lds, st);
@@ -1437,7 +1511,14 @@ escg_status escg_step_mcs(const escg_params *p, uint8_t *d_lattice,
     if (!d_lattice || !aligned4(d_lattice))
         return ESCG_EINVAL;
     hipStream_t st = S_(stream);
-    const Derived d = derive(p);
+    Derived d = derive(p);
+    StreamBuf abuf(st);
+    if (d.prob) {
+        s = upload_words(d.ab, abuf);
+        if (s != ESCG_OK)
+            return s;
+        d.d_ab = static_cast<const uint32_t *>(abuf.ptr);
+    }
     const uint32_t L = p->L, S = p->S, N = L * L;
     const bool persistent = (L & 7u) == 0 && L >= g_tiled_min_L.load();
     if (!persistent && L <= std::min(g_single_lds_max_L.load(), lds_max_L(S))) {
@@ -1517,7 +1598,14 @@ escg_status escg_run_until_extinction(const escg_params *p, uint8_t *d_lattice,
         mode > ESCG_STOP_NONE)
         return ESCG_EINVAL;
     hipStream_t st = S_(stream);
-    const Derived d = derive(p);
+    Derived d = derive(p);
+    StreamBuf abuf(st);
+    if (d.prob) {
+        s = upload_words(d.ab, abuf);
+        if (s != ESCG_OK)
+            return s;
+        d.d_ab = static_cast<const uint32_t *>(abuf.ptr);
+    }
     const uint32_t L = p->L, S = p->S, N = L * L;
     if ((L & 7u) == 0 && L >= g_tiled_min_L.load()) {
         s = run_until_persistent(p, d, d_lattice, mcs0, max_mcs, mode,
@@ -1715,10 +1803,26 @@ escg_status escg_step_batch(uint32_t n, const escg_params *h_params,
         std::vector<uint32_t> wg_end(m);
         size_t scratch_bytes = 0, lds = 0;
         uint32_t wg = 0;
+        // with any job carrying dominance probabilities the group runs the
+        // probabilistic kernel; the others then get thresholds from their
+        // 0/1 matrix (the same rule)
+        bool prob = false;
+        for (uint32_t j : idx)
+            prob = prob || h_params[j].dom_prob != nullptr;
+        const uint32_t Sp = packed ? 8u : 32u, abw = 2u * Sp * Sp;
+        std::vector<uint32_t> ab_all;
+        if (prob)
+            ab_all.resize((size_t)m * abw);
         for (uint32_t i = 0; i < m; ++i) {
             const uint32_t j = idx[i];
             const escg_params *p = &h_params[j];
             const Derived d = derive(p);
+            if (prob) {
+                const std::vector<uint32_t> ab =
+                    selection_thresholds(p, d.T1, d.T2);
+                std::copy(ab.begin(), ab.end(),
+                          ab_all.begin() + (size_t)i * abw);
+            }
             BatchStepJob &J = tbl[i];
             std::memset(&J, 0, sizeof(J));
             J.lattice = h_lattices[j];
@@ -1739,14 +1843,26 @@ escg_status escg_step_batch(uint32_t n, const escg_params *h_params,
             lds = std::max(lds, plans[j].lds);
         }
         const size_t tbl_bytes = (sizeof(BatchStepJob) * m + 255) & ~(size_t)255;
+        const size_t ab_bytes = ab_all.size() * 4;
         uint8_t *dev = nullptr;
-        if (hipMallocAsync((void **)&dev, tbl_bytes + scratch_bytes, st) !=
+        if (hipMallocAsync((void **)&dev,
+                           tbl_bytes + ((ab_bytes + 255) & ~(size_t)255) +
+                               scratch_bytes,
+                           st) !=
             hipSuccess)
             return ESCG_ENOMEM;
-        size_t off = tbl_bytes;
+        const uint32_t *d_ab = reinterpret_cast<const uint32_t *>(dev + tbl_bytes);
+        size_t off = tbl_bytes + ((ab_bytes + 255) & ~(size_t)255);
         for (uint32_t i = 0; i < m; ++i) {
             tbl[i].scratch = dev + off;
+            tbl[i].ab = prob ? d_ab + (size_t)i * abw : nullptr;
             off += ((size_t)tbl[i].G.L * tbl[i].G.L + 255) & ~(size_t)255;
+        }
+        if (prob &&
+            hipMemcpyAsync(dev + tbl_bytes, ab_all.data(), ab_bytes,
+                           hipMemcpyHostToDevice, st) != hipSuccess) {
+            (void)hipFreeAsync(dev, st);
+            return ESCG_EDEVICE;
         }
         BatchStepJob *d_tbl = reinterpret_cast<BatchStepJob *>(dev);
         if (hipMemcpyAsync(d_tbl, tbl.data(), sizeof(BatchStepJob) * m,
@@ -1754,8 +1870,8 @@ escg_status escg_step_batch(uint32_t n, const escg_params *h_params,
             (void)hipFreeAsync(dev, st);
             return ESCG_EDEVICE;
         }
-        const void *fn = packed ? (const void *)tiled_step_batch_kernel<true>
-                                : (const void *)tiled_step_batch_kernel<false>;
+        const void *fn =
+            ESCG_KERNEL2(tiled_step_batch_kernel, packed == 1, prob);
         allow_dynamic_lds(fn, lds);
         uint32_t active = m;
         const uint32_t steps = h_n_mcs[idx[0]];
@@ -1763,14 +1879,11 @@ escg_status escg_step_batch(uint32_t n, const escg_params *h_params,
             while (active > 0 && h_n_mcs[idx[active - 1]] <= k)
                 --active;
             const uint32_t grid = wg_end[active - 1];
-            if (packed)
-                hipLaunchKernelGGL(tiled_step_batch_kernel<true>, dim3(grid),
-                                   dim3(kBatchStepThreads), lds, st, d_tbl,
-                                   active, k);
-            else
-                hipLaunchKernelGGL(tiled_step_batch_kernel<false>, dim3(grid),
-                                   dim3(kBatchStepThreads), lds, st, d_tbl,
-                                   active, k);
+            const BatchStepJob *tp = d_tbl;
+            uint32_t na = active, kk = k;
+            void *args[] = {&tp, &na, &kk};
+            (void)hipLaunchKernel(fn, dim3(grid), dim3(kBatchStepThreads), args,
+                                  lds, st);
         }
         // an odd number of steps leaves the state in the scratch buffer
         for (uint32_t i = 0; i < m; ++i)
@@ -1828,6 +1941,12 @@ escg_status escg_batch_run(uint32_t n, const escg_params *h_params,
             if (sp[j].first < sp[j - 1].second)
                 return ESCG_EINVAL;
     }
+    // one kernel instantiation serves the whole batch: with any S > 7 job
+    // every job runs with the larger S > 7 tables and must fit beside them
+    if (!all_small)
+        for (uint32_t j = 0; j < n; ++j)
+            if (h_params[j].L > lds_max_L(ESCG_MAX_SPECIES))
+                return ESCG_EINVAL;
     // Longest jobs first (cost ~ L^2 * MCS budget).
     for (uint32_t j = 0; j < n; ++j)
         order[j] = j;
@@ -1836,27 +1955,51 @@ escg_status escg_batch_run(uint32_t n, const escg_params *h_params,
         const double cb = (double)jobs[b].L * jobs[b].L * jobs[b].max_mcs;
         return ca > cb;
     });
+    // with any job carrying dominance probabilities the batch runs the
+    // probabilistic kernel; every job then gets selection thresholds (from
+    // its 0/1 matrix when it has no probabilities: the same rule), with the
+    // kernel's table stride
+    bool prob = false;
+    for (uint32_t j = 0; j < n; ++j)
+        prob = prob || h_params[j].dom_prob != nullptr;
+    const uint32_t Sp = all_small ? 8u : 32u, abw = 2u * Sp * Sp;
+    std::vector<uint32_t> ab_all;
+    if (prob) {
+        ab_all.resize((size_t)n * abw);
+        for (uint32_t j = 0; j < n; ++j) {
+            const std::vector<uint32_t> ab = selection_thresholds(
+                &h_params[j], jobs[j].T1, jobs[j].T2, Sp);
+            std::copy(ab.begin(), ab.end(), ab_all.begin() + (size_t)j * abw);
+        }
+    }
     hipStream_t st = S_(stream);
     const size_t tbl = sizeof(JobDev) * n, ord = sizeof(uint32_t) * n;
+    const size_t ab_off = (tbl + ord + 256 + 255) & ~(size_t)255;
     uint8_t *dev = nullptr;
-    if (hipMallocAsync((void **)&dev, tbl + ord + 256, st) != hipSuccess)
+    if (hipMallocAsync((void **)&dev, ab_off + ab_all.size() * 4, st) !=
+        hipSuccess)
         return ESCG_ENOMEM;
     JobDev *d_jobs = reinterpret_cast<JobDev *>(dev);
     uint32_t *d_order = reinterpret_cast<uint32_t *>(dev + tbl);
     uint32_t *d_queue = reinterpret_cast<uint32_t *>(dev + tbl + ord + 128);
+    if (prob)
+        for (uint32_t j = 0; j < n; ++j)
+            jobs[j].ab =
+                reinterpret_cast<const uint32_t *>(dev + ab_off) + (size_t)j * abw;
     escg_status s = ESCG_OK;
     if (hipMemcpyAsync(d_jobs, jobs.data(), tbl, hipMemcpyHostToDevice, st) !=
             hipSuccess ||
         hipMemcpyAsync(d_order, order.data(), ord, hipMemcpyHostToDevice,
-                       st) != hipSuccess) {
+                       st) != hipSuccess ||
+        (prob && hipMemcpyAsync(dev + ab_off, ab_all.data(), ab_all.size() * 4,
+                                hipMemcpyHostToDevice, st) != hipSuccess)) {
         (void)hipFreeAsync(dev, st);
         return ESCG_EDEVICE;
     }
     launch_fill(d_queue, 1, 0, st);
     const size_t lds = lds_need;
     const uint32_t nt = lds_threads(Lmax);
-    const void *fn = all_small ? (const void *)lds_batch_kernel<true>
-                               : (const void *)lds_batch_kernel<false>;
+    const void *fn = ESCG_KERNEL2(lds_batch_kernel, all_small, prob);
     allow_dynamic_lds(fn, lds);
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nt, lds) !=
@@ -1866,13 +2009,13 @@ escg_status escg_batch_run(uint32_t n, const escg_params *h_params,
     const DeviceInfo di = device_info();
     const uint32_t grid =
         std::min<uint32_t>(n, (uint32_t)std::max(1, di.cus) * per_cu);
-    if (all_small)
-        hipLaunchKernelGGL(lds_batch_kernel<true>, dim3(grid), dim3(nt), lds,
-                           st, d_jobs, d_order, n, d_queue, d_lattices);
-    else
-        hipLaunchKernelGGL(lds_batch_kernel<false>, dim3(grid), dim3(nt), lds,
-                           st, d_jobs, d_order, n, d_queue, d_lattices);
-    s = last_hip(hipGetLastError());
+    const JobDev *aj = d_jobs;
+    const uint32_t *ao = d_order;
+    uint32_t an = n;
+    uint32_t *aq = d_queue;
+    uint8_t *al = d_lattices;
+    void *args[] = {&aj, &ao, &an, &aq, &al};
+    s = last_hip(hipLaunchKernel(fn, dim3(grid), dim3(nt), args, lds, st));
     (void)hipFreeAsync(dev, st);
     return s;
 }

@@ -158,13 +158,19 @@ __device__ __forceinline__ void pair_rule(uint32_t u, uint32_t T1, uint32_t T2,
 // block's top-left, top-right, bottom-left and bottom-right sites.  Von
 // Neumann: bits 0-1 of w pick the edge, bit 2 the orientation; Moore: bits
 // 0-2 pick one of the eight pair slots (edges, then the diagonals (A,D),
-// (B,C) twice each), bit 3 the orientation.
+// (B,C) twice each), bit 3 the orientation.  ab (global, or null): the
+// selection thresholds of a job with dominance probabilities, A at
+// [x * Sp + y] and B at [Sp * Sp + x * Sp + y]; a selection draw u then
+// compares v = u - T1 with them (v < A: the selected cell wins, else
+// v < B: the neighbour wins, else nothing).
 template <class Dom>
 __device__ __forceinline__ void update_block(uint8_t *lat, uint32_t pA,
                                              uint32_t pB, uint32_t pC,
                                              uint32_t pD, uint32_t w,
                                              uint32_t T1, uint32_t T2,
-                                             const Dom &d, bool moore)
+                                             const Dom &d, bool moore,
+                                             const uint32_t *ab = nullptr,
+                                             uint32_t Sp = 8)
 {
     const uint32_t e = moore ? (w & 7u) : (w & 3u);
     const uint32_t o = moore ? (w >> 3) & 1u : (w >> 2) & 1u;
@@ -180,7 +186,19 @@ __device__ __forceinline__ void update_block(uint8_t *lat, uint32_t pA,
         s = t;
     }
     uint32_t x = lat[f], y = lat[s];
-    pair_rule(w >> 8, T1, T2, d, x, y);
+    const uint32_t u = w >> 8;
+    if (ab && u >= T1 && u < T2) {
+        if (x != y && x != 0 && y != 0) {
+            const uint32_t i = (x & (Sp - 1)) * Sp + (y & (Sp - 1));
+            const uint32_t v = u - T1;
+            if (v < ab[i])
+                y = 0;
+            else if (v < ab[Sp * Sp + i])
+                x = 0;
+        }
+    } else {
+        pair_rule(u, T1, T2, d, x, y);
+    }
     lat[f] = (uint8_t)x;
     lat[s] = (uint8_t)y;
 }

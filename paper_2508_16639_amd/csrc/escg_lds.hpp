@@ -15,7 +15,10 @@ namespace escg {
 template <int SP>
 struct LdsTables {
     uint2 sel[256];               // {gather, scatter} selectors
-    uint16_t rule[3 * SP * SP];   // (x', y') per action, x, y
+    uint16_t rule[6 * SP * SP];   // (x', y') per action (3 used without
+                                  // dominance probabilities), x, y
+    uint32_t ab[2 * SP * SP];     // selection thresholds A, B per (x, y)
+                                  // (jobs with dominance probabilities)
     uint32_t dom[32];             // dominance masks
     uint32_t cnt[64];             // two count rows
     uint32_t misc[4];
@@ -66,11 +69,12 @@ __device__ inline LdsWalk lds_walk(uint32_t L, uint32_t LS)
 
 // Pass p of MCS t for this thread's quads; w = word p of the MCS's offset
 // draw (ox = bit 0, oy = bit 1, uniform).
+template <class Ctx>
 __device__ __forceinline__ void lds_pass(uint8_t *lat, uint32_t L,
                                          uint32_t LS, const LdsWalk &W,
                                          uint32_t w, uint32_t p, uint32_t t,
                                          uint32_t replica, uint32_t k0,
-                                         uint32_t k1, const QuadCtx &qc)
+                                         uint32_t k1, const Ctx &qc)
 {
     const uint32_t Lb = L >> 1;
     const uint32_t ox = w & 1u, oy = (w >> 1) & 1u;
@@ -106,10 +110,11 @@ __device__ __forceinline__ void lds_pass(uint8_t *lat, uint32_t L,
 
 // One MCS (four passes) on an L x L lattice held whole in LDS with row
 // stride LS.
+template <class Ctx>
 __device__ __forceinline__ void lds_mcs(uint8_t *lat, uint32_t L, uint32_t LS,
                                         uint32_t t, uint32_t replica,
                                         uint32_t k0, uint32_t k1,
-                                        const QuadCtx &qc, const LdsWalk &W)
+                                        const Ctx &qc, const LdsWalk &W)
 {
     const Words off = philox10(0u, t, kTagOffset << 8, replica, k0, k1);
 #pragma unroll
@@ -120,35 +125,48 @@ __device__ __forceinline__ void lds_mcs(uint8_t *lat, uint32_t L, uint32_t LS,
     }
 }
 
-template <int SP>
-__device__ inline QuadCtx make_quad_ctx(const LdsTables<SP> &T, uint32_t T1,
-                                        uint32_t T2)
+template <bool kProb = false, int SP>
+__device__ inline QuadCtxT<kProb> make_quad_ctx(const LdsTables<SP> &T,
+                                                uint32_t T1, uint32_t T2)
 {
-    QuadCtx qc;
+    QuadCtxT<kProb> qc;
     qc.sel = T.sel;
     qc.rule = reinterpret_cast<const uint8_t *>(T.rule);
     const ActionSplit a = split_actions(T1, T2);
+    const uint32_t tb = SP * SP * 2u; // bytes per rule table
     qc.W1 = a.W1;
     qc.W2 = a.W2;
-    qc.B1 = a.a1 * SP * SP * 2u;
-    qc.B2 = a.a2 * SP * SP * 2u;
-    qc.B3 = a.a3 * SP * SP * 2u;
+    qc.B1 = a.a1 * tb;
+    qc.B2 = a.a2 * tb;
+    qc.B3 = a.a3 * tb;
     qc.dotw = (2u * SP) | (2u << 8);
+    qc.ab = reinterpret_cast<const uint8_t *>(T.ab);
+    qc.abw = (4u * SP) | (4u << 8);
+    qc.boff = SP * SP * 4u;
+    qc.T1 = T1;
+    qc.Bsel = 1u * tb;
+    qc.Bo = 3u * tb;
+    qc.so = tb;
     return qc;
 }
 
 // Fills the tables of a job (dominance masks from `dom`, global or LDS;
-// `moore`: the 8-way neighbourhood's pair slots).
+// `moore`: the 8-way neighbourhood's pair slots; `ab`: the selection
+// thresholds A, B (2 * SP * SP u32, global) of a job with dominance
+// probabilities, else null).
 template <int SP>
 __device__ inline void setup_tables(LdsTables<SP> &T, const uint32_t *dom,
-                                    bool moore)
+                                    bool moore, const uint32_t *ab = nullptr)
 {
     for (uint32_t i = threadIdx.x; i < 32; i += blockDim.x)
         T.dom[i] = dom[i];
     for (uint32_t i = threadIdx.x; i < 64; i += blockDim.x)
         T.cnt[i] = 0;
+    if (ab)
+        for (uint32_t i = threadIdx.x; i < 2 * SP * SP; i += blockDim.x)
+            T.ab[i] = ab[i];
     __syncthreads();
-    build_quad_luts(T.sel, T.rule, SP, T.dom, moore);
+    build_quad_luts(T.sel, T.rule, SP, T.dom, moore, ab != nullptr);
     __syncthreads();
 }
 

@@ -25,14 +25,28 @@
 
 namespace escg {
 
-// Per-job constants of the quad update (all uniform).
-struct QuadCtx {
+// Per-job constants of the quad update (all uniform).  kProb: the job has
+// dominance probabilities; a selection then looks up the pair's thresholds
+// A, B (LDS tables of Sp*Sp u32 each) and compares v = u - T1 with them:
+// v < A the selected cell wins, else v < B the neighbour wins, else nothing.
+// Those three outcomes are rule tables 3, 4, 5.
+template <bool kProb>
+struct QuadCtxT {
+    static constexpr bool kProbabilistic = kProb;
     const uint2 *sel;     // LDS: 256 {gather, scatter} selectors
     const uint8_t *rule;  // LDS: rule tables, byte addressed
     uint32_t W1, W2;      // word-space thresholds (w <= W1: first table ...)
     uint32_t B1, B2, B3;  // byte offsets of the three rule tables to use
     uint32_t dotw;        // {2*Sp, 2, 0, 0}
+    // kProb only
+    const uint8_t *ab;    // LDS: A table, then B table (Sp*Sp u32 each)
+    uint32_t abw;         // {4*Sp, 4, 0, 0}
+    uint32_t boff;        // byte offset of the B table from A
+    uint32_t T1;          // selection draws are u = T1 .. T2 - 1
+    uint32_t Bsel;        // byte offset of the deterministic selection table
+    uint32_t Bo, so;      // outcome tables: Bo + {0, so, 2 so}
 };
+using QuadCtx = QuadCtxT<false>;
 
 // Host-computed word-space thresholds and table choice for (T1, T2) in
 // [0, 2^24]: first = w <= W1 ? B1 : (w <= W2 ? B2 : B3), equivalent to
@@ -64,13 +78,15 @@ __host__ __device__ inline ActionSplit split_actions(uint32_t T1, uint32_t T2)
     return s;
 }
 
-// Builds the selector table (2 KB) and the rule tables (3*Sp*Sp u16) in LDS
-// with the workgroup's threads.  dom: 32 dominance masks (LDS or global).
+// Builds the selector table (2 KB) and the rule tables (3*Sp*Sp u16, plus
+// the three selection outcomes when `prob`: 6*Sp*Sp) in LDS with the
+// workgroup's threads.  dom: 32 dominance masks (LDS or global).
 // Von Neumann: bits 0-1 of the block word pick the edge, bit 2 the
 // orientation.  Moore: bits 0-2 pick one of eight pair slots (the four
 // edges, then the diagonals (A,D), (B,C) twice each), bit 3 the orientation.
 __device__ inline void build_quad_luts(uint2 *sel, uint16_t *rule, uint32_t Sp,
-                                       const uint32_t *dom, bool moore)
+                                       const uint32_t *dom, bool moore,
+                                       bool prob = false)
 {
     for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) {
         const uint32_t e = moore ? (i & 7u) : (i & 3u);
@@ -107,6 +123,20 @@ __device__ inline void build_quad_luts(uint2 *sel, uint16_t *rule, uint32_t Sp,
         pair_rule(u, 1u, 2u, dt, x, y);
         rule[i] = (uint16_t)(x | (y << 8));
     }
+    if (!prob)
+        return;
+    // selection outcomes: 3 the selected cell wins, 4 the neighbour wins,
+    // 5 nothing; a win needs two different occupied sites
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const uint32_t a = i / (Sp * Sp), xy = i - a * Sp * Sp;
+        uint32_t x = xy / Sp, y = xy - (xy / Sp) * Sp;
+        const bool fight = x != y && x != 0 && y != 0;
+        if (fight && a == 0)
+            y = 0;
+        else if (fight && a == 1)
+            x = 0;
+        rule[n + i] = (uint16_t)(x | (y << 8));
+    }
 }
 
 __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo,
@@ -116,8 +146,9 @@ __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo,
 }
 
 // One block: B = [A, B, C, D] -> updated dword.
+template <class Ctx>
 __device__ __forceinline__ uint32_t block_update(uint32_t B, uint32_t w,
-                                                 const QuadCtx &c)
+                                                 const Ctx &c)
 {
     const uint2 s = c.sel[w & 0xFFu];
     const uint32_t xy = perm(B, B, s.x);
@@ -126,6 +157,16 @@ __device__ __forceinline__ uint32_t block_update(uint32_t B, uint32_t w,
     const uint32_t b1 = c.B1, b2 = c.B2, b3 = c.B3;
     uint32_t base = (w <= c.W2) ? b2 : b3;
     base = (w <= c.W1) ? b1 : base;
+    if constexpr (Ctx::kProbabilistic) {
+        const uint32_t ai = __builtin_amdgcn_udot4(xy, c.abw, 0u, false);
+        const uint32_t A = *reinterpret_cast<const uint32_t *>(c.ab + ai);
+        const uint32_t Bt =
+            *reinterpret_cast<const uint32_t *>(c.ab + c.boff + ai);
+        const uint32_t v = (w >> 8) - c.T1;
+        const uint32_t so = c.so, zero = 0u;
+        const uint32_t o = c.Bo + ((v >= A) ? so : zero) + ((v >= Bt) ? so : zero);
+        base = (base == c.Bsel) ? o : base;
+    }
     const uint32_t off = __builtin_amdgcn_udot4(xy, c.dotw, base, false);
     const uint32_t out = *reinterpret_cast<const uint16_t *>(c.rule + off);
     return perm(out, B, s.y);
@@ -133,9 +174,10 @@ __device__ __forceinline__ uint32_t block_update(uint32_t B, uint32_t w,
 
 // Row segments (8 bytes each, little-endian: byte k = column k of the
 // segment) -> four updated segments in place.
+template <class Ctx>
 __device__ __forceinline__ void quad_update(uint32_t &a0, uint32_t &a1,
                                             uint32_t &c0, uint32_t &c1,
-                                            const Words &w, const QuadCtx &c)
+                                            const Words &w, const Ctx &c)
 {
     // transpose: block j = [a(2j), a(2j+1), c(2j), c(2j+1)]
     uint32_t b0 = perm(a0, c0, 0x01000504u);
@@ -154,9 +196,10 @@ __device__ __forceinline__ void quad_update(uint32_t &a0, uint32_t &a1,
 }
 
 // Quad whose columns start 8-byte aligned in LDS (offset ox = 0).
+template <class Ctx>
 __device__ __forceinline__ void quad_even(uint8_t *lat, uint32_t pa,
                                           uint32_t pc, const Words &w,
-                                          const QuadCtx &c)
+                                          const Ctx &c)
 {
     uint2 ra = *reinterpret_cast<const uint2 *>(lat + pa);
     uint2 rc = *reinterpret_cast<const uint2 *>(lat + pc);
@@ -168,10 +211,11 @@ __device__ __forceinline__ void quad_even(uint8_t *lat, uint32_t pa,
 // Quad whose columns start one byte after an 8-byte boundary (ox = 1):
 // pa / pc are the aligned addresses, ea / ec the addresses of the ninth byte
 // (the column after the 8-byte boundary, possibly wrapped by the caller).
+template <class Ctx>
 __device__ __forceinline__ void quad_odd(uint8_t *lat, uint32_t pa,
                                          uint32_t pc, uint32_t ea,
                                          uint32_t ec, const Words &w,
-                                         const QuadCtx &c)
+                                         const Ctx &c)
 {
     const uint2 ra = *reinterpret_cast<const uint2 *>(lat + pa);
     const uint2 rc = *reinterpret_cast<const uint2 *>(lat + pc);
@@ -196,10 +240,11 @@ __device__ __forceinline__ void quad_odd(uint8_t *lat, uint32_t pa,
 
 // One block addressed site by site (irregular quads: lattice edges with
 // wrap inside the quad, or blocks past the row end).
+template <class Ctx>
 __device__ __forceinline__ void block_bytes(uint8_t *lat, uint32_t pA,
                                             uint32_t pB, uint32_t pC,
                                             uint32_t pD, uint32_t w,
-                                            const QuadCtx &c)
+                                            const Ctx &c)
 {
     uint32_t B = (uint32_t)lat[pA] | ((uint32_t)lat[pB] << 8) |
                  ((uint32_t)lat[pC] << 16) | ((uint32_t)lat[pD] << 24);

@@ -124,11 +124,12 @@ __host__ __device__ inline uint32_t tile_threads(const TileGeom &G,
 
 // Pass p of MCS t for this thread's quads; w = word p of the MCS's offset
 // draw (ox = bit 0, oy = bit 1, uniform).
+template <class Ctx>
 __device__ __forceinline__ void tile_pass(uint8_t *lat, const TileGeom &G,
                                           const TileWalk &W, uint32_t w,
                                           uint32_t p, uint32_t t,
                                           uint32_t replica, uint32_t k0,
-                                          uint32_t k1, const QuadCtx &qc)
+                                          uint32_t k1, const Ctx &qc)
 {
     const uint32_t LS = G.LS();
     const uint32_t ox = w & 1u, oy = (w >> 1) & 1u;
@@ -157,10 +158,11 @@ __device__ __forceinline__ void tile_pass(uint8_t *lat, const TileGeom &G,
 }
 
 // One MCS over the region: all quads of all block rows, four passes.
+template <class Ctx>
 __device__ __forceinline__ void tile_mcs(uint8_t *lat, const TileGeom &G,
                                          const TileWalk &W, uint32_t t,
                                          uint32_t replica, uint32_t k0,
-                                         uint32_t k1, const QuadCtx &qc)
+                                         uint32_t k1, const Ctx &qc)
 {
     const Words off = philox10(0u, t, kTagOffset << 8, replica, k0, k1);
 #pragma unroll

@@ -42,7 +42,8 @@ class CParams(C.Structure):
                 ("dom", C.c_uint32 * 32),
                 ("rate_ex", C.c_double), ("rate_sel", C.c_double),
                 ("rate_rep", C.c_double), ("seed", C.c_uint64),
-                ("replica", C.c_uint32), ("flags", C.c_uint32)]
+                ("replica", C.c_uint32), ("flags", C.c_uint32),
+                ("dom_prob", C.c_void_p)]
 
 
 EXPORTS = ("escg_status_str", "escg_last_error", "escg_circulant_dom", "escg_dom_from_matrix",
@@ -140,6 +141,7 @@ class Params:
     seed: int = 1
     replica: int = 0
     moore: bool = False      # 8-way (Moore) instead of 4-way neighbourhood
+    prob: Optional[object] = None  # S x S dominance probabilities or None
 
     def c(self) -> CParams:
         p = CParams()
@@ -151,6 +153,14 @@ class Params:
         p.seed = int(self.seed) & 0xFFFFFFFFFFFFFFFF
         p.replica = int(self.replica) & 0xFFFFFFFF
         p.flags = FLAG_MOORE if self.moore else 0
+        if self.prob is not None:
+            P = np.ascontiguousarray(self.prob, dtype=np.float64).reshape(-1)
+            if P.size != self.S * self.S:
+                raise ValueError("prob must hold S * S entries")
+            p.dom_prob = P.ctypes.data
+            p._keep = P  # the array must outlive the call
+        else:
+            p.dom_prob = None
         return p
 
 
@@ -328,8 +338,9 @@ def batch_run(params: Sequence[Params], offsets, lattices, max_mcs,
     int32 device tensor of n * 34 words."""
     n = len(params)
     arr = (CParams * max(n, 1))()
-    for i, p in enumerate(params):
-        arr[i] = p.c()
+    keep = [p.c() for p in params]  # holds any probability arrays
+    for i, cp in enumerate(keep):
+        arr[i] = cp
     off = np.ascontiguousarray(offsets, dtype=np.uint64)
     mx = np.ascontiguousarray(max_mcs, dtype=np.uint32)
     m0 = (np.ascontiguousarray(mcs0, dtype=np.uint32)
@@ -358,8 +369,9 @@ def step_batch(params: Sequence[Params], lattices, mcs0, n_mcs,
     assert len(lattices) == n and len(mcs0) == n and len(n_mcs) == n
     arr = (CParams * max(n, 1))()
     ptrs = (C.c_void_p * max(n, 1))()
-    for i, (p, t) in enumerate(zip(params, lattices)):
-        arr[i] = p.c()
+    keep = [p.c() for p in params]  # holds any probability arrays
+    for i, (cp, p, t) in enumerate(zip(keep, params, lattices)):
+        arr[i] = cp
         ptrs[i] = _ptr(t, "torch.uint8", p.L * p.L).value
     m0 = np.ascontiguousarray(mcs0, dtype=np.uint32)
     nm = np.ascontiguousarray(n_mcs, dtype=np.uint32)

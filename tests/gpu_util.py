@@ -7,15 +7,25 @@ from paper_2508_16639_amd import escg
 
 
 def pair(L, S, K, ex, sel=1.0, rep=1.0, seed=1, replica=0, D=None,
-         moore=False):
+         moore=False, P=None):
     """The same job for the HIP library (escg.Params) and the oracle."""
     if D is None:
         D = O.circulant_matrix(S, K) if K else np.zeros((S, S), np.uint8)
     p = escg.Params(L=L, S=S, dom=escg.dom_from_matrix(D), ex=ex, sel=sel,
-                    rep=rep, seed=seed, replica=replica, moore=moore)
+                    rep=rep, seed=seed, replica=replica, moore=moore, prob=P)
     j = O.Job(L, S, D, ex, sel, rep, seed=seed, replica=replica,
-              nbhd=8 if moore else 4)
+              nbhd=8 if moore else 4, P=P)
     return p, j
+
+
+def probabilities(D, seed=0):
+    """Seeded dominance probabilities on the edges of D (zeros elsewhere),
+    some at the ends 0 and 1."""
+    rng = np.random.default_rng(seed)
+    P = rng.uniform(0.05, 0.95, size=D.shape) * (D != 0)
+    P[(D != 0) & (rng.random(D.shape) < 0.15)] = 1.0
+    P[(D != 0) & (rng.random(D.shape) < 0.1)] = 0.0
+    return P
 
 
 def dev(a, device="cuda:0"):

@@ -145,6 +145,17 @@ def test_unknown_flag_bits_rejected(flags):
                                     None, None) == escg.EINVAL
 
 
+@pytest.mark.parametrize("bad", [-0.1, 1.5, float("nan"), float("inf")])
+def test_dominance_probabilities_outside_unit_interval_rejected(bad):
+    D = np.array([[0, 1, 0], [0, 0, 1], [1, 0, 0]], np.uint8)
+    P = D * 0.5
+    P[1, 0] = bad   # even where D has no edge: every entry must be in [0, 1]
+    cp = escg.Params(L=8, S=3, dom=escg.dom_from_matrix(D), ex=1.0,
+                     prob=P).c()
+    assert escg.lib().escg_step_mcs(C.byref(cp), C.c_void_p(4096), 0, 1,
+                                    None, None) == escg.EINVAL
+
+
 def test_moore_flag_is_bit_zero():
     assert escg.FLAG_MOORE == 1
     cp = escg.Params(L=8, S=3, dom=escg.circulant_dom(3, [1]), ex=1.0,

@@ -8,7 +8,7 @@ import oracle as O
 from paper_2508_16639_amd import escg
 from paper_2508_16639_amd.workloads import (RPS64, RPS512, RPSLS3200,
                                             random_lattice)
-from tests.gpu_util import dev, host, pair
+from tests.gpu_util import dev, host, pair, probabilities
 
 pytestmark = pytest.mark.gpu
 
@@ -189,6 +189,109 @@ def test_moore_step_batch_and_batch_run_match_oracle():
     r = O.o2_run_until(j, g, 0, 300, O.FIRST_EXTINCTION)
     assert np.array_equal(host(res)[:6], r)
     assert np.array_equal(host(buf), g)
+
+
+PROB_CASES = [
+    # L, S, K, (ex, sel, rep), n_mcs, moore
+    (2, 3, [1], (0.5, 2.0, 1.0), 20, False),
+    (16, 5, [1, 3], (1.0, 2.0, 1.0), 8, True),
+    (64, 3, [1], (0.5, 1.0, 1.0), 8, False),
+    (64, 9, [1, 2, 4], (0.0, 1.0, 1.0), 5, False),
+    (100, 7, [1, 2, 4], (1.0, 1.0, 0.0), 4, True),
+    (130, 5, [1, 3], (1.0, 1.0, 1.0), 3, False),
+    (200, 3, [1], (51.2, 1.0, 1.0), 3, False),
+    (404, 13, [1, 2, 5], (1.0, 1.0, 1.0), 2, False),
+    (520, 5, [1, 3], (5.0, 1.0, 1.0), 2, True),
+]
+
+
+@pytest.mark.parametrize("case", PROB_CASES, ids=lambda c: f"L{c[0]}_S{c[1]}")
+@pytest.mark.parametrize("route", ["auto", "tiled", "lds", "persistent"])
+def test_probabilistic_dominance_step_mcs_bit_exact(case, route):
+    L, S, K, rates, n, moore = case
+    if route in ("tiled", "persistent") and L < 16:
+        pytest.skip("tiled paths not used below L=16")
+    if route == "lds" and L > escg.batch_max_L(S):
+        pytest.skip("lattice does not fit LDS")
+    route_to(route)
+    D = O.circulant_matrix(S, K)
+    D[0, 1] = 1 - D[0, 1]          # not circulant: one edge flipped
+    P = probabilities(D, seed=L + S)
+    p, j = pair(L, S, None, *rates, seed=L + 3, replica=2, D=D, moore=moore,
+                P=P)
+    g0 = random_lattice(L, S, seed=L + 11, domain=2)
+    out, c = gpu_step(p, g0, 9, n, route=route)
+    ref = g0.copy()
+    rc = O.o2_run(j, ref, 9, n)
+    assert np.array_equal(out, ref)
+    assert np.array_equal(c, rc)
+
+
+@pytest.mark.parametrize("route", ["lds", "tiled", "persistent"])
+def test_probabilities_equal_to_matrix_reproduce_deterministic_bytes(route):
+    route_to(route)
+    D = O.circulant_matrix(5, [1, 3])
+    pd, _ = pair(136, 5, None, 1.0, D=D)
+    pp, _ = pair(136, 5, None, 1.0, D=D, P=D.astype(np.float64))
+    g0 = random_lattice(136, 5, seed=4)
+    a, ca = gpu_step(pd, g0, 0, 4, route=route)
+    b, cb = gpu_step(pp, g0, 0, 4, route=route)
+    assert np.array_equal(a, b) and np.array_equal(ca, cb)
+
+
+def test_probabilistic_batches_and_run_until_match_oracle():
+    # a batch mixing deterministic and probabilistic jobs, both kernel
+    # instantiations; the batched per-MCS step; run-until on the
+    # persistent kernel
+    D3, D9 = O.circulant_matrix(3, [1]), O.circulant_matrix(9, [1, 2, 4])
+    jobs = []
+    for i, (L, D, prob) in enumerate([(32, D3, True), (48, D3, False),
+                                      (64, D9, True), (40, D9, False)]):
+        P = probabilities(D, seed=i) if prob else None
+        jobs.append(pair(L, D.shape[0], None, 2.0, seed=6, replica=i, D=D,
+                         P=P))
+    offs, off = [], 0
+    for p, _ in jobs:
+        offs.append(off)
+        off += p.L * p.L
+    buf = torch.zeros(off, dtype=torch.uint8, device="cuda:0")
+    res = torch.full((len(jobs) * escg.BATCH_RESULT_WORDS,), -1,
+                     dtype=torch.int32, device="cuda:0")
+    escg.batch_run([p for p, _ in jobs], offs, buf, [40] * len(jobs),
+                   escg.STOP_MONOCULTURE, True, res)
+    r = host(res).reshape(len(jobs), escg.BATCH_RESULT_WORDS)
+    out = host(buf)
+    for (p, j), o, rr in zip(jobs, offs, r):
+        g = j.init()
+        ref = O.o2_run_until(j, g, 0, 40, O.MONOCULTURE)
+        assert np.array_equal(rr[:p.S + 3], ref)
+        assert np.array_equal(out[o:o + p.L * p.L], g)
+    specs = [(16, D3, True, 3), (136, D3, False, 2), (64, D9, True, 1)]
+    ps, js, lats, g0s = [], [], [], []
+    for i, (L, D, prob, n) in enumerate(specs):
+        P = probabilities(D, seed=10 + i) if prob else None
+        p, j = pair(L, D.shape[0], None, 0.9, seed=90 + i, D=D, P=P)
+        g0 = random_lattice(L, D.shape[0], seed=i, domain=2)
+        ps.append(p)
+        js.append(j)
+        g0s.append(g0)
+        lats.append(dev(g0))
+    escg.step_batch(ps, lats, [2] * len(specs), [s[3] for s in specs])
+    for (L, D, prob, n), j, g0, lat in zip(specs, js, g0s, lats):
+        ref = g0.copy()
+        O.o2_run(j, ref, 2, n)
+        assert np.array_equal(host(lat), ref), (L, prob)
+    D = np.array([[0, 1, 1], [0, 0, 0], [0, 0, 0]], np.uint8)
+    P = np.array([[0, 0.4, 0.7], [0, 0, 0], [0, 0, 0]])
+    p, j = pair(96, 3, None, 0.5, 1.0, 1.0, seed=8, D=D, P=P)
+    g0 = j.init()
+    lat = dev(g0)
+    res = torch.full((6,), -1, dtype=torch.int32, device="cuda:0")
+    escg.run_until_extinction(p, lat, 0, 3000, escg.STOP_MONOCULTURE, res)
+    assert escg.last_route() == "persistent"
+    ref = g0.copy()
+    r = O.o2_run_until(j, ref, 0, 3000, O.MONOCULTURE)
+    assert np.array_equal(host(res), r) and np.array_equal(host(lat), ref)
 
 
 def _imported_matrices():
