@@ -9,7 +9,8 @@ table of command-line parameters; CUDA section, additional flags):
 (4 = von Neumann, 8 = Moore), --printFrequency, --mobility
 (eps = M * L^2 / 2, escg_eps_from_mobility), --species, --flux (periodic
 boundaries only), --empty (initial empty-site probability), --save,
---dominance (import a dominance CSV; it sets the species count), --resume
+--dominance (import a dominance CSV; it sets the species count, and
+entries strictly between 0 and 1 are win probabilities), --resume
 (continue a saved run).  --numRandoms and --maxStep are accepted and have no
 effect: random numbers are drawn inside the kernels, and a single launch
 already runs many MCS.
@@ -106,8 +107,8 @@ class Run:
         resume = args.resume
         if resume:
             prm = escg_io.read_params_csv(os.path.join(resume, "params.csv"))
-            D = escg_io.read_dominance_csv(os.path.join(resume,
-                                                        "dominance.csv"))
+            D, P = escg_io.read_dominance_probabilities_csv(
+                os.path.join(resume, "dominance.csv"))
             g, L, done = escg_io.read_grid_csv(os.path.join(resume,
                                                             "grid.csv"))
             self.L, self.S = L, D.shape[0]
@@ -117,7 +118,7 @@ class Run:
             self.replica = int(prm["replica"])
             self.sel = float(prm["selection"])
             self.rep = float(prm["reproduction"])
-            self.D = D
+            self.D, self.P = D, P
             self.done = done
             self.lattice0 = g
         else:
@@ -130,7 +131,8 @@ class Run:
             if args.dominance:
                 path = ("dominance.csv" if str(args.dominance).lower() ==
                         "true" else args.dominance)
-                self.D = escg_io.read_dominance_csv(path)
+                self.D, self.P = escg_io.read_dominance_probabilities_csv(
+                    path)
                 self.S = self.D.shape[0]
             else:
                 self.S = args.species
@@ -140,6 +142,7 @@ class Run:
                 self.D = np.array([[(dom[a] >> b) & 1
                                     for b in range(1, self.S + 1)]
                                    for a in range(1, self.S + 1)], np.uint8)
+                self.P = None
             self.moore = args.neighbourhood == 8
             self.mobility = args.mobility
             self.seed, self.replica = args.seed, args.replica
@@ -151,7 +154,8 @@ class Run:
         self.p = escg.Params(L=self.L, S=self.S,
                              dom=escg.dom_from_matrix(self.D), ex=eps,
                              sel=self.sel, rep=self.rep, seed=self.seed,
-                             replica=self.replica, moore=self.moore)
+                             replica=self.replica, moore=self.moore,
+                             prob=self.P)
         self.lat = torch.empty(self.N, dtype=torch.uint8, device="cuda")
         if self.lattice0 is not None:
             if int(self.lattice0.max()) > self.S:
@@ -213,7 +217,8 @@ def main(argv: Optional[List[str]] = None) -> int:
         os.makedirs(out, exist_ok=True)
         escg_io.write_params_csv(os.path.join(out, "params.csv"),
                                  run.params_record())
-        escg_io.write_dominance_csv(os.path.join(out, "dominance.csv"), run.D)
+        escg_io.write_dominance_csv(os.path.join(out, "dominance.csv"), run.D,
+                                    run.P)
     dens = os.path.join(out, "densities.csv") if out else None
     c0 = torch.empty(run.S + 1, dtype=torch.int32, device="cuda")
     escg.densities(run.p, run.lat, c0)

@@ -3,10 +3,11 @@ snapshots, run parameters and the per-MCS density record, all as CSV.
 
 Formats follow the paper's program (Sec. "Single Threaded ESCG in C++":
 dominance import; CUDA section: save / resume):
-  * dominance CSV: S rows of S comma-separated 0/1 entries, row i = species
+  * dominance CSV: S rows of S comma-separated entries, row i = species
     i+1, column j = species j+1, 1 = row species beats column species
     (the paper's flat matrix layout of Algorithm "Dominance Check"); the
-    number of rows sets S;
+    number of rows sets S; entries strictly between 0 and 1 are win
+    probabilities (probabilistic dominance);
   * grid CSV: one line per lattice row of comma-separated site values
     (0 = empty, 1..S species), then one line with the number of MCS done;
   * params CSV: `name,value` lines;
@@ -26,27 +27,43 @@ import numpy as np
 def read_dominance_csv(path: str) -> np.ndarray:
     """S x S uint8 matrix (0/1) from a dominance CSV; raises ValueError on a
     non-square matrix, entries other than 0/1 or S outside 1..31."""
+    D, P = read_dominance_probabilities_csv(path)
+    if P is not None:
+        raise ValueError(f"{path}: entries must be 0 or 1")
+    return D
+
+
+def read_dominance_probabilities_csv(path: str):
+    """(D, P) from a dominance CSV whose entries are win probabilities in
+    [0, 1] (the probabilistic interactions of the Park, Chen and Szolnoki
+    replication): D = (entry > 0) as uint8, P the float matrix, or None when
+    every entry is 0 or 1 (a deterministic matrix)."""
     rows = []
     with open(path, newline="") as f:
         for line in csv.reader(f):
             cells = [c.strip() for c in line if c.strip() != ""]
             if cells:
-                rows.append([int(float(c)) for c in cells])
+                rows.append([float(c) for c in cells])
     S = len(rows)
     if not 1 <= S <= 31 or any(len(r) != S for r in rows):
         raise ValueError(f"{path}: expected a square matrix with 1..31 rows")
-    D = np.asarray(rows, dtype=np.int64)
-    if not np.isin(D, (0, 1)).all():
-        raise ValueError(f"{path}: entries must be 0 or 1")
-    return D.astype(np.uint8)
+    P = np.asarray(rows, dtype=np.float64)
+    if not ((P >= 0.0) & (P <= 1.0)).all():
+        raise ValueError(f"{path}: entries must lie in [0, 1]")
+    D = (P > 0.0).astype(np.uint8)
+    return D, (None if np.isin(P, (0.0, 1.0)).all() else P)
 
 
-def write_dominance_csv(path: str, D: np.ndarray) -> None:
-    D = np.asarray(D, dtype=np.uint8)
+def write_dominance_csv(path: str, D: np.ndarray, P=None) -> None:
+    """Writes D (0/1), or the probabilities P where given (exact reprs)."""
     with open(path, "w", newline="") as f:
         w = csv.writer(f)
-        for row in D:
-            w.writerow([int(v) for v in row])
+        if P is None:
+            for row in np.asarray(D, dtype=np.uint8):
+                w.writerow([int(v) for v in row])
+        else:
+            for row in np.asarray(P, dtype=np.float64):
+                w.writerow([repr(float(v)) for v in row])
 
 
 def write_grid_csv(path: str, lattice: np.ndarray, L: int, mcs: int) -> None:

@@ -74,3 +74,17 @@ def test_paper_flags_parse_with_defaults():
     a = cli.build_parser().parse_args(["--maxStep", "true", "--numRandoms",
                                        "1000", "--dominance", "true"])
     assert a.maxStep is True and a.dominance == "true"
+
+
+def test_dominance_csv_with_probabilities(tmp_path):
+    P = np.array([[0, 0.25, 1.0], [0, 0, 0.5], [0.75, 0, 0]])
+    f = tmp_path / "dominance.csv"
+    escg_io.write_dominance_csv(str(f), (P > 0).astype(np.uint8), P)
+    D, back = escg_io.read_dominance_probabilities_csv(str(f))
+    assert np.array_equal(D, (P > 0).astype(np.uint8))
+    assert np.array_equal(back, P)
+    with pytest.raises(ValueError):
+        escg_io.read_dominance_csv(str(f))   # not a 0/1 matrix
+    f.write_text("0,1\n1,0\n")
+    D, back = escg_io.read_dominance_probabilities_csv(str(f))
+    assert back is None and D.tolist() == [[0, 1], [1, 0]]

@@ -81,3 +81,19 @@ def test_cli_moore_run_and_resume_match_oracle(tmp_path):
     ref = job.init()
     O.o2_run(job, ref, 0, 20, want_counts=False)
     assert np.array_equal(g, ref)
+
+
+def test_cli_probabilistic_dominance_matches_oracle(tmp_path):
+    P = np.array([[0, 0.3, 0.0], [0.0, 0, 0.6], [0.9, 0.0, 0]])
+    f = tmp_path / "dominance.csv"
+    escg_io.write_dominance_csv(str(f), (P > 0).astype(np.uint8), P)
+    d = str(tmp_path / "run")
+    _run(["--length", "40", "--mobility", "1e-4", "--seed", "2", "--quiet",
+          "--printFrequency", "10", "--mcs", "25", "--dominance", str(f),
+          "--save", d])
+    g, L, mcs = escg_io.read_grid_csv(d + "/grid.csv")
+    D = (P > 0).astype(np.uint8)
+    job = O.Job(40, 3, D, eps_from_mobility(1e-4, 40), seed=2, P=P)
+    ref = job.init()
+    O.o2_run(job, ref, 0, mcs, want_counts=False)
+    assert np.array_equal(g, ref)
