@@ -175,8 +175,20 @@ def serving(args, torch, escg, workloads):
     return serve.bench_serving(torch, escg, workloads)
 
 
+def host_cpu() -> str:
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model or 'unknown CPU'}, {os.cpu_count()} logical CPUs visible"
+
+
 def cpu_baseline(w):
-    import numpy as np
     import oracle as O
     n = 50
     job = O.Job(w.L, w.S, O.circulant_matrix(w.S, w.K), w.ex, w.sel, w.rep,
@@ -186,12 +198,54 @@ def cpu_baseline(w):
     c = O.o2_run(job, g, 0, n)
     dt = time.perf_counter() - t0
     assert (c.sum(1) == w.L * w.L).all()
-    del np
     return {"value": float(w.L) ** 2 * n / dt, "unit": "site-updates/s",
             "cores": 1, "kind": "oracle",
             "sample": f"oracle (same block schedule, plain C, one thread): "
                       f"L={w.L} RPSLS init + {n} of the {w.mcs} MCS with "
-                      f"per-MCS counts, {dt:.1f} s"}
+                      f"per-MCS counts, {dt:.1f} s; host {host_cpu()}"}
+
+
+def _o2_replica(args):
+    import oracle as O
+    L, S, K, ex, seed, replica, n = args
+    job = O.Job(L, S, O.circulant_matrix(S, K), ex, seed=seed,
+                replica=replica)
+    g = job.init()
+    O.o2_run(job, g, 0, n, want_counts=False)
+    return L * L * n
+
+
+def cpu_context(w):
+    """Further CPU figures beside the baseline: the paper-style random-
+    sequential oracle (O1) on one thread, and the block-schedule oracle on
+    every core with one replica per process (independent replicas are the
+    CPU's natural parallelism)."""
+    import multiprocessing as mp
+    import oracle as O
+    job = O.Job(w.L, w.S, O.circulant_matrix(w.S, w.K), w.ex, w.sel, w.rep,
+                seed=w.seed, replica=w.replica)
+    g = job.init()
+    n1 = 10
+    t0 = time.perf_counter()
+    O.o1_run(job, g, 0, n1, want_counts=False)
+    d1 = time.perf_counter() - t0
+    cores = max(1, min(16, os.cpu_count() or 1))
+    L, n = 800, 200  # per replica: 1.28e8 site-updates
+    tasks = [(L, w.S, list(w.K), w.ex, w.seed, r, n) for r in range(cores)]
+    t0 = time.perf_counter()
+    with mp.Pool(cores) as pool:
+        su = sum(pool.map(_o2_replica, tasks))
+    dall = time.perf_counter() - t0
+    return {"o1_one_thread": {"value": float(w.L) ** 2 * n1 / d1,
+                              "unit": "site-updates/s",
+                              "sample": f"L={w.L} RPSLS, {n1} MCS, "
+                                        f"{d1:.1f} s"},
+            "o2_all_cores": {"value": su / dall, "unit": "site-updates/s",
+                             "cores": cores,
+                             "sample": f"{cores} replicas of L={L} RPSLS "
+                                       f"x {n} MCS, one per process, "
+                                       f"{dall:.1f} s"},
+            "host": host_cpu()}
 
 
 def main():
@@ -286,6 +340,8 @@ def main():
         out["serving"] = serving(args, torch, escg, workloads)
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(w)
+        log("[bench] cpu context (O1, all-core O2)")
+        out["cpu_context"] = cpu_context(w)
     print(json.dumps(out), flush=True)
 
 
