@@ -44,12 +44,26 @@ __device__ inline void tile_load(uint8_t *lat, const uint8_t *g,
 {
     const uint32_t L = G.L, LS = G.LS(), R0 = ty * G.TH, g0 = tx * G.TW;
     const uint32_t dwr = (G.TW + 16) >> 2, rows = G.RH();
+    // (r, j) advance by (dr, dj) with a carry: no division in the loop; the
+    // global row R0 - 4 + r and column g0 - 8 + 4 j lie in (-8, L + 8), so
+    // adding L and subtracting it at most twice wraps them
+    uint32_t r = threadIdx.x / dwr, j = threadIdx.x - r * dwr;
+    const uint32_t dr = blockDim.x / dwr, dj = blockDim.x - dr * dwr;
     for (uint32_t i = threadIdx.x; i < rows * dwr; i += blockDim.x) {
-        const uint32_t r = i / dwr, j = i - r * dwr;
-        const uint32_t gr = (R0 + L - 4 + r) % L;
-        const uint32_t gc = (g0 + L - 8 + 4 * j) % L;
+        uint32_t gr = R0 + L - 4 + r;
+        gr = min(gr, gr - L);
+        gr = min(gr, gr - L);
+        uint32_t gc = g0 + L - 8 + 4 * j;
+        gc = min(gc, gc - L);
+        gc = min(gc, gc - L);
         *reinterpret_cast<uint32_t *>(lat + r * LS + 4 * j) =
             *reinterpret_cast<const uint32_t *>(g + (size_t)gr * L + gc);
+        j += dj;
+        r += dr;
+        if (j >= dwr) {
+            j -= dwr;
+            ++r;
+        }
     }
     // spare columns (read only by the last odd-offset quad of a row)
     for (uint32_t r = threadIdx.x; r < rows; r += blockDim.x)
@@ -62,11 +76,18 @@ __device__ inline void tile_store(const uint8_t *lat, uint8_t *g,
 {
     const uint32_t L = G.L, LS = G.LS(), R0 = ty * G.TH, g0 = tx * G.TW;
     const uint32_t dwr = G.TW >> 2;
+    uint32_t r = threadIdx.x / dwr, j = threadIdx.x - r * dwr;
+    const uint32_t dr = blockDim.x / dwr, dj = blockDim.x - dr * dwr;
     for (uint32_t i = threadIdx.x; i < G.TH * dwr; i += blockDim.x) {
-        const uint32_t r = i / dwr, j = i - r * dwr;
         *reinterpret_cast<uint32_t *>(g + (size_t)(R0 + r) * L + g0 + 4 * j) =
             *reinterpret_cast<const uint32_t *>(lat + (r + 4) * LS + 8 +
                                                 4 * j);
+        j += dj;
+        r += dr;
+        if (j >= dwr) {
+            j -= dwr;
+            ++r;
+        }
     }
 }
 
