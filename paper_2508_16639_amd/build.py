@@ -14,6 +14,7 @@ SOURCES = [os.path.join(CSRC, "escg.hip")]
 HEADERS = [os.path.join(CSRC, "escg_device.hpp"),
            os.path.join(CSRC, "escg_quad.hpp"),
            os.path.join(CSRC, "escg_lds.hpp"),
+           os.path.join(CSRC, "escg_tile.hpp"),
            os.path.join(INCLUDE, "escg.h")]
 ARCH = "gfx950"
 

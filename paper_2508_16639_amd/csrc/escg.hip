@@ -449,6 +449,7 @@ __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
 {
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ LdsTables<kPacked ? 8 : 32> TB;
+    __shared__ __align__(16) uint32_t s_part[8 * kCountSlots];
     uint32_t *s_cnt = TB.cnt;
     uint32_t *s_misc = TB.misc;
     uint8_t *lat = smem;
@@ -465,6 +466,8 @@ __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
 
     if (tid == 0)
         s_misc[0] = 0;
+    for (uint32_t i = tid; i < 8 * kCountSlots; i += blockDim.x)
+        s_part[i] = 0;
     tile_load(lat, a.lattice, G, ty, tx);
     setup_tables(TB, a.dom, a.moore != 0, kProb ? a.ab : nullptr);
     const auto qc = make_quad_ctx<kProb>(TB, a.T1, a.T2); // after a barrier
@@ -483,9 +486,9 @@ __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
             lat, a.exch, G, ty, tx, slot, tag, a.abort, a.spin_limit, [&] {
                 if (a.counts) {
                     if (kPacked)
-                        tile_count<8>(lat, G, S, s_cnt);
+                        tile_count_sums(lat, G, S, s_part);
                     else
-                        tile_count<32>(lat, G, S, s_cnt);
+                        tile_count_wide(lat, G, S, s_cnt);
                 }
             });
         if (st) {
@@ -496,9 +499,15 @@ __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
             s_misc[0] = 1;
         }
         __syncthreads();
-        if (a.counts && tid <= S) {
-            atomicAdd(&a.counts[(size_t)(t + 1) * (S + 1) + tid], s_cnt[tid]);
-            s_cnt[tid] = 0;
+        if (a.counts) {
+            uint32_t *row = a.counts + (size_t)(t + 1) * (S + 1);
+            if constexpr (kPacked) {
+                if (tid < 64) // one wave; the slots are next used 4 barriers on
+                    tile_count_flush(s_part, S, G.TH * G.TW, row);
+            } else if (tid <= S) {
+                atomicAdd(&row[tid], s_cnt[tid]);
+                s_cnt[tid] = 0;
+            }
         }
         if (s_misc[0]) {
             aborted = true;
@@ -530,6 +539,7 @@ __global__ __launch_bounds__(512) void tiled_step_kernel(StepArgs a)
 {
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ LdsTables<kPacked ? 8 : 32> TB;
+    __shared__ __align__(16) uint32_t s_part[8 * kCountSlots];
     uint32_t *s_cnt = TB.cnt;
     uint8_t *lat = smem;
     const TileGeom G = a.G;
@@ -545,6 +555,8 @@ __global__ __launch_bounds__(512) void tiled_step_kernel(StepArgs a)
         }
         return;
     }
+    for (uint32_t i = tid; i < 8 * kCountSlots; i += blockDim.x)
+        s_part[i] = 0;
     tile_load(lat, a.src, G, ty, tx);
     setup_tables(TB, a.dom, a.moore != 0, kProb ? a.ab : nullptr);
     const auto qc = make_quad_ctx<kProb>(TB, a.T1, a.T2);
@@ -553,12 +565,16 @@ __global__ __launch_bounds__(512) void tiled_step_kernel(StepArgs a)
     tile_store(lat, a.dst, G, ty, tx);
     if (a.counts) {
         if (kPacked)
-            tile_count<8>(lat, G, S, s_cnt);
+            tile_count_sums(lat, G, S, s_part);
         else
-            tile_count<32>(lat, G, S, s_cnt);
+            tile_count_wide(lat, G, S, s_cnt);
         __syncthreads();
-        if (tid <= S && s_cnt[tid])
+        if constexpr (kPacked) {
+            if (tid < 64)
+                tile_count_flush(s_part, S, G.TH * G.TW, a.counts);
+        } else if (tid <= S && s_cnt[tid]) {
             atomicAdd(&a.counts[tid], s_cnt[tid]);
+        }
     }
 }
 
@@ -1029,8 +1045,8 @@ struct TiledPlan {
 };
 
 // Workgroup size for a tile (0: the tile is too wide): see tile_threads;
-// tile_count walks one column of dword pairs per thread, so TW / 8 threads
-// are needed (TW / 4 for S > 7).
+// the counts walk one column of dword pairs per thread (tile_count_sums), so
+// TW / 8 threads are needed (TW / 4 for S > 7, tile_count_wide).
 uint32_t tiled_threads(const TileGeom &G, uint32_t cap)
 {
     const uint32_t nt = std::max(64u, tile_threads(G, cap));

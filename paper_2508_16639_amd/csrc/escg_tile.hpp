@@ -392,19 +392,16 @@ __device__ inline uint32_t tile_gather(uint8_t *lat, const uint32_t *nb,
                        [] {});
 }
 
-// Adds the interior's species counts into cnt[0..S] (LDS, zeroed).  SM == 8:
-// one-hot byte codes (values 0..7), two dwords per step (TW % 8 == 0 keeps
-// the pairs inside a row and 8-byte aligned); else byte compares per species.
-// A thread walks one column of pairs down the rows (rstep rows apart), so
-// its LDS address advances by a constant.
-template <int SM>
-__device__ __forceinline__ void tile_count(const uint8_t *lat,
-                                           const TileGeom &G, uint32_t S,
-                                           uint32_t *cnt)
+// Species counts of the interior, S > 7: byte compares per species, added
+// into cnt[0..S] (LDS, zeroed).  A thread walks one column of dwords down the
+// rows (rstep rows apart), so its LDS address advances by a constant.
+__device__ __forceinline__ void tile_count_wide(const uint8_t *lat,
+                                                const TileGeom &G, uint32_t S,
+                                                uint32_t *cnt)
 {
-    constexpr uint32_t per = SM == 8 ? 8u : 4u;
-    const uint32_t LS = G.LS(), dwr = G.TW / per;
-    const uint32_t rstep = blockDim.x / dwr; // >= 1: TW / 8 <= blockDim
+    constexpr int SM = 32;
+    const uint32_t LS = G.LS(), dwr = G.TW / 4;
+    const uint32_t rstep = blockDim.x / dwr; // >= 1: TW / 4 <= blockDim
     const uint32_t r0 = threadIdx.x / dwr, j = threadIdx.x - r0 * dwr;
     uint32_t c[SM];
 #pragma unroll
@@ -412,42 +409,185 @@ __device__ __forceinline__ void tile_count(const uint8_t *lat,
         c[s] = 0;
     uint32_t mine = 0;
     if (r0 < rstep) {
-        const uint8_t *p0 = lat + (4 + r0) * LS + 8 + per * j;
-        if constexpr (SM == 8) {
-            // one loop per species range: absent species cost nothing
-            auto walk = [&](auto ns) {
-                const uint8_t *p = p0;
-                for (uint32_t r = r0; r < G.TH; r += rstep, p += rstep * LS) {
-                    const uint2 v = *reinterpret_cast<const uint2 *>(p);
-                    count_pair8<decltype(ns)::value>(v.x, v.y, c);
-                }
-            };
-            if (S < 4)
-                walk(std::integral_constant<int, 4>{});
-            else if (S < 6)
-                walk(std::integral_constant<int, 6>{});
-            else
-                walk(std::integral_constant<int, 8>{});
-        } else {
-            const uint8_t *p = p0;
-            for (uint32_t r = r0; r < G.TH; r += rstep, p += rstep * LS) {
-                const uint32_t v = *reinterpret_cast<const uint32_t *>(p);
-                ++mine;
+        const uint8_t *p = lat + (4 + r0) * LS + 8 + 4 * j;
+        for (uint32_t r = r0; r < G.TH; r += rstep, p += rstep * LS) {
+            const uint32_t v = *reinterpret_cast<const uint32_t *>(p);
+            ++mine;
 #pragma unroll
-                for (int s = 0; s < SM; ++s)
-                    if ((uint32_t)s <= S)
-                        c[s] += bytes_ne(v, (uint32_t)s);
-            }
+            for (int s = 0; s < SM; ++s)
+                if ((uint32_t)s <= S)
+                    c[s] += bytes_ne(v, (uint32_t)s);
         }
     }
 #pragma unroll
     for (int s = 0; s < SM; ++s) {
         if ((uint32_t)s <= S) {
-            const uint32_t tot = wave_sum(SM == 8 ? c[s] : 4u * mine - c[s]);
+            const uint32_t tot = wave_sum(4u * mine - c[s]);
             if ((threadIdx.x & 63u) == 0 && tot)
                 atomicAdd(&cnt[s], tot);
         }
     }
+}
+
+// Species counts of the interior, S <= 7 (site values 0..7), without one
+// popcount or reduction per species.  With NS = 4, 6 or 8 states covering
+// 0..S, the interior's counts n_s follow from NS - 1 linear sums:
+//   q = 0 .. NS-3: n_{q+1} (species 1 .. NS-2),
+//   q = NS-2:      V = sum of the site values,
+// then n_{NS-1} = (V - sum_{s=1}^{NS-2} s n_s) / (NS - 1) (exact) and
+// n_0 = sites - sum_{s>=1} n_s.
+// Species 2p+1 and 2p+2 share one v_perm code table (value 2p+1 -> 0x01,
+// 2p+2 -> 0x10, other values -> 0): summed bytewise, the low nibbles of the
+// codes count species 2p+1 and the high nibbles 2p+2, and v_dot8_u32_u4
+// adds up either set of nibbles.  V is summed bytewise too (v_add3), then
+// by v_dot4.  A nibble gains at most 2 per row (two dwords per row), so rows
+// are taken in groups of at most 7; a V byte stays below 7 * 14.
+// Each thread walks one column of dword pairs (as tile_count_wide, eight
+// sites per row) and adds its NS - 1 sums into LDS slots
+// part[q * 32 + (lane & 31)] (atomics, so any number of threads may share a
+// slot); tile_count_flush reduces the slots after a barrier.
+constexpr uint32_t kCountSlots = 32;
+
+__host__ __device__ inline uint32_t count_states(uint32_t S)
+{
+    return S < 4 ? 4u : (S < 6 ? 6u : 8u);
+}
+
+__host__ __device__ constexpr uint64_t pair_code_table(int p)
+{
+    return (0x01ull << (8 * (2 * p + 1))) | (0x10ull << (8 * (2 * p + 2)));
+}
+
+template <int NS>
+__device__ __forceinline__ void tile_count_sums(const uint8_t *lat,
+                                                const TileGeom &G,
+                                                uint32_t *part)
+{
+    constexpr int NP = (NS - 2) / 2; // code tables
+    const uint32_t LS = G.LS(), dwr = G.TW >> 3;
+    const uint32_t rstep = blockDim.x / dwr; // >= 1: TW / 8 <= blockDim
+    const uint32_t r0 = threadIdx.x / dwr, j = threadIdx.x - r0 * dwr;
+    uint32_t n[NS - 1];
+#pragma unroll
+    for (int q = 0; q < NS - 1; ++q)
+        n[q] = 0;
+    if (r0 < rstep) {
+        const uint8_t *p = lat + (4 + r0) * LS + 8 + 8 * j;
+        const uint32_t pstep = rstep * LS;
+        uint32_t r = r0;
+        while (r < G.TH) {
+            uint32_t sv = 0, cp[NP];
+#pragma unroll
+            for (int k = 0; k < NP; ++k)
+                cp[k] = 0;
+            for (uint32_t g = 0; g < 7 && r < G.TH; ++g) {
+                const uint2 v = *reinterpret_cast<const uint2 *>(p);
+                sv += v.x + v.y;
+#pragma unroll
+                for (int k = 0; k < NP; ++k) {
+                    const uint64_t t = pair_code_table(k);
+                    const uint32_t hi = (uint32_t)(t >> 32), lo = (uint32_t)t;
+                    cp[k] += __builtin_amdgcn_perm(hi, lo, v.x) +
+                             __builtin_amdgcn_perm(hi, lo, v.y);
+                }
+                r += rstep;
+                p += pstep;
+            }
+            n[NS - 2] = __builtin_amdgcn_udot4(sv, 0x01010101u, n[NS - 2],
+                                               false);
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                n[2 * k] = __builtin_amdgcn_udot8(cp[k], 0x01010101u,
+                                                  n[2 * k], false);
+                n[2 * k + 1] = __builtin_amdgcn_udot8(cp[k], 0x10101010u,
+                                                      n[2 * k + 1], false);
+            }
+        }
+    }
+    uint32_t *slot = part + (threadIdx.x & (kCountSlots - 1));
+#pragma unroll
+    for (int q = 0; q < NS - 1; ++q)
+        atomicAdd(slot + q * kCountSlots, n[q]);
+}
+
+__device__ inline void tile_count_sums(const uint8_t *lat, const TileGeom &G,
+                                       uint32_t S, uint32_t *part)
+{
+    const uint32_t ns = count_states(S);
+    if (ns == 4)
+        tile_count_sums<4>(lat, G, part);
+    else if (ns == 6)
+        tile_count_sums<6>(lat, G, part);
+    else
+        tile_count_sums<8>(lat, G, part);
+}
+
+// Flush, step 1 (lane of the flushing wave): the sum of slots 4j .. 4j+3 of
+// sum q = lane / 8, j = lane % 8, which it also clears; 0 for q >= nq.
+__device__ __forceinline__ uint32_t count_slot_sum(uint32_t *part,
+                                                   uint32_t lane, uint32_t nq)
+{
+    const uint32_t q = lane >> 3, j = lane & 7u;
+    if (q >= nq)
+        return 0;
+    uint4 *p = reinterpret_cast<uint4 *>(part + q * kCountSlots + 4 * j);
+    const uint4 x = *p;
+    *p = make_uint4(0u, 0u, 0u, 0u);
+    return x.x + x.y + x.z + x.w;
+}
+
+// Flush, step 3: the count of species s from the NS - 1 sums T (uniform).
+template <int NS>
+__device__ __forceinline__ uint32_t count_species(uint32_t s,
+                                                  const uint32_t (&T)[NS - 1],
+                                                  uint32_t sites)
+{
+    uint32_t direct = 0, weighted = 0, v = 0;
+#pragma unroll
+    for (int q = 0; q < NS - 2; ++q) {
+        direct += T[q];
+        weighted += (uint32_t)(q + 1) * T[q];
+        v = (s == (uint32_t)q + 1) ? T[q] : v;
+    }
+    const uint32_t last = (T[NS - 2] - weighted) / (uint32_t)(NS - 1);
+    v = (s == (uint32_t)NS - 1) ? last : v;
+    return (s == 0) ? sites - direct - last : v;
+}
+
+// Adds the interior's counts (from the slots, which it clears) to
+// row[0..S] (global atomics).  Called by all 64 lanes of one wave after a
+// barrier that follows tile_count_sums; step 2 adds the eight partial sums
+// of each q with DPP (quad swaps, then row_shr:4 so that lane 8q+4 holds the
+// total).
+template <int NS>
+__device__ __forceinline__ void tile_count_flush(uint32_t *part, uint32_t S,
+                                                 uint32_t sites,
+                                                 uint32_t *row)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t v = count_slot_sum(part, lane, NS - 1);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, true);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, true);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);
+    uint32_t T[NS - 1];
+#pragma unroll
+    for (int q = 0; q < NS - 1; ++q)
+        T[q] = (uint32_t)__builtin_amdgcn_readlane((int)v, 8 * q + 4);
+    const uint32_t c = count_species<NS>(lane, T, sites);
+    if (lane <= S && c)
+        atomicAdd(row + lane, c);
+}
+
+__device__ inline void tile_count_flush(uint32_t *part, uint32_t S,
+                                        uint32_t sites, uint32_t *row)
+{
+    const uint32_t ns = count_states(S);
+    if (ns == 4)
+        tile_count_flush<4>(part, S, sites, row);
+    else if (ns == 6)
+        tile_count_flush<6>(part, S, sites, row);
+    else
+        tile_count_flush<8>(part, S, sites, row);
 }
 
 } // namespace escg
