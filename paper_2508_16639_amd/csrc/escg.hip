@@ -472,6 +472,7 @@ __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
     setup_tables(TB, a.dom, a.moore != 0, kProb ? a.ab : nullptr);
     const auto qc = make_quad_ctx<kProb>(TB, a.T1, a.T2); // after a barrier
     const TileWalk W = tile_walk(G, ty, tx);
+    const HaloPlan HP = halo_plan(a.exch, G, ty, tx);
 
     bool aborted = false;
     for (uint32_t t = 0; t < a.n_mcs; ++t) {
@@ -483,7 +484,8 @@ __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
         // the tags replace flags: each halo word is awaited on its own; the
         // counts run while the first halo loads are in flight
         const uint32_t st = tile_gather(
-            lat, a.exch, G, ty, tx, slot, tag, a.abort, a.spin_limit, [&] {
+            lat, a.exch, HP, G, ty, tx, slot * T * sd, tag, a.abort,
+            a.spin_limit, [&] {
                 if (a.counts) {
                     if (kPacked)
                         tile_count_sums(lat, G, S, s_part);

@@ -336,47 +336,79 @@ __device__ __forceinline__ uint32_t await_word(const uint32_t *src,
     return 0;
 }
 
-// Rebuilds the halo from the neighbours' strips in slot `s` once they carry
-// `tag`.  Each thread keeps two words in flight; `between()` runs after the
-// first loads are issued and before they are awaited (every thread calls it
+// A thread's first two halo words (i = tid and tid + blockDim), fixed for
+// the run: dword offsets of their sources from the start of exchange slot 0
+// and their LDS destinations.  Later words (only when the halo has more than
+// 2 * blockDim words) are mapped on the fly.
+struct HaloPlan {
+    uint32_t n;            // halo words
+    uint32_t src_a, src_b; // dword offsets into slot 0
+    uint32_t dst_a, dst_b; // LDS byte offsets
+};
+
+__device__ inline HaloPlan halo_plan(const uint32_t *nb, const TileGeom &G,
+                                     uint32_t ty, uint32_t tx)
+{
+    const HaloMap M(nb, G, ty, tx, 0);
+    HaloPlan P;
+    P.n = M.count();
+    const uint32_t i = threadIdx.x, bd = blockDim.x;
+    const HaloWord a = M.at(i < P.n ? i : 0), b = M.at(i + bd < P.n ? i + bd : 0);
+    P.src_a = (uint32_t)(a.src - nb);
+    P.src_b = (uint32_t)(b.src - nb);
+    P.dst_a = a.dst;
+    P.dst_b = b.dst;
+    return P;
+}
+
+// Rebuilds the halo from the neighbours' strips in exchange slot `s`
+// (dword offset s_off = s * tiles * slot_dwords) once they carry `tag`.
+// Each thread keeps two words in flight; `between()` runs after the first
+// loads are issued and before they are awaited (every thread calls it
 // exactly once, so it may contain wave-wide operations), which hides the
 // load latency behind other work.  Returns the worst await_word status of
 // this thread (0 = all words arrived).
 template <class Fn>
 __device__ inline uint32_t tile_gather(uint8_t *lat, const uint32_t *nb,
-                                       const TileGeom &G, uint32_t ty,
-                                       uint32_t tx, uint32_t s, uint32_t tag,
+                                       const HaloPlan &P, const TileGeom &G,
+                                       uint32_t ty, uint32_t tx,
+                                       uint32_t s_off, uint32_t tag,
                                        const uint32_t *abort,
                                        uint32_t spin_limit, Fn &&between)
 {
-    const HaloMap M(nb, G, ty, tx, s);
-    const uint32_t n = M.count(), bd = blockDim.x;
+    const uint32_t n = P.n, bd = blockDim.x;
     uint32_t i = threadIdx.x;
     bool one = i < n, two = i + bd < n;
-    HaloWord a = M.at(one ? i : 0), b = M.at(two ? i + bd : 0);
-    uint32_t va = one ? xload(a.src) : 0u;
-    uint32_t vb = two ? xload(b.src) : 0u;
+    const uint32_t *sa = nb + s_off + P.src_a, *sb = nb + s_off + P.src_b;
+    uint32_t da = P.dst_a, db = P.dst_b;
+    uint32_t va = one ? xload(sa) : 0u;
+    uint32_t vb = two ? xload(sb) : 0u;
     between();
     uint32_t status = 0;
     while (one) {
-        status = await_word(a.src, tag, va, abort, spin_limit);
+        status = await_word(sa, tag, va, abort, spin_limit);
         if (!status && two)
-            status = await_word(b.src, tag, vb, abort, spin_limit);
+            status = await_word(sb, tag, vb, abort, spin_limit);
         if (status)
             break;
-        *reinterpret_cast<uint32_t *>(lat + a.dst) = va & 0x7F7F7F7Fu;
+        *reinterpret_cast<uint32_t *>(lat + da) = va & 0x7F7F7F7Fu;
         if (two)
-            *reinterpret_cast<uint32_t *>(lat + b.dst) = vb & 0x7F7F7F7Fu;
+            *reinterpret_cast<uint32_t *>(lat + db) = vb & 0x7F7F7F7Fu;
         i += 2 * bd;
         one = i < n;
         two = i + bd < n;
         if (one) {
-            a = M.at(i);
-            va = xload(a.src);
-        }
-        if (two) {
-            b = M.at(i + bd);
-            vb = xload(b.src);
+            const HaloMap M(nb + s_off, G, ty, tx, 0);
+            const HaloWord a = M.at(i);
+            sa = a.src;
+            da = a.dst;
+            va = xload(sa);
+            if (two) {
+                const HaloWord b = M.at(i + bd);
+                sb = b.src;
+                db = b.dst;
+                vb = xload(sb);
+            }
         }
     }
     return status;
@@ -388,8 +420,10 @@ __device__ inline uint32_t tile_gather(uint8_t *lat, const uint32_t *nb,
                                        const uint32_t *abort,
                                        uint32_t spin_limit)
 {
-    return tile_gather(lat, nb, G, ty, tx, s, tag, abort, spin_limit,
-                       [] {});
+    const HaloPlan P = halo_plan(nb, G, ty, tx);
+    return tile_gather(lat, nb, P, G, ty, tx,
+                       s * G.TY * G.TX * G.slot_dwords(), tag, abort,
+                       spin_limit, [] {});
 }
 
 // Species counts of the interior, S > 7: byte compares per species, added
