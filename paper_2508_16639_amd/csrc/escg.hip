@@ -440,6 +440,7 @@ struct TiledArgs {
     uint64_t seed;
     TileGeom G;
     uint32_t S, T1, T2, replica, mcs0, n_mcs, spin_limit, moore;
+    uint32_t list;        // quads by TileList (else TileWalk)
     const uint32_t *ab;   // selection thresholds (global) or null
     uint32_t dom[32];
 };
@@ -475,46 +476,59 @@ __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
     const HaloPlan HP = halo_plan(a.exch, G, ty, tx);
 
     bool aborted = false;
-    for (uint32_t t = 0; t < a.n_mcs; ++t) {
-        tile_mcs(lat, G, W, a.mcs0 + t, a.replica, k0, k1, qc);
-        // publish, count and gather touch disjoint parts of the region:
-        // border strips and interior are read, only the halo is written
-        const uint32_t e = t + 1, slot = exch_slot(e), tag = exch_tag(e);
-        tile_publish(lat, a.exch + (size_t)(slot * T + tile) * sd, G, tag);
-        // the tags replace flags: each halo word is awaited on its own; the
-        // counts run while the first halo loads are in flight
-        const uint32_t st = tile_gather(
-            lat, a.exch, HP, G, ty, tx, slot * T * sd, tag, a.abort,
-            a.spin_limit, [&] {
-                if (a.counts) {
-                    if (kPacked)
-                        tile_count_sums(lat, G, S, s_part);
-                    else
-                        tile_count_wide(lat, G, S, s_cnt);
+    // the MCS loop, with the quad walk of the passes as a parameter
+    auto run = [&](auto &&mcs) {
+        for (uint32_t t = 0; t < a.n_mcs; ++t) {
+            mcs(a.mcs0 + t);
+            // publish, count and gather touch disjoint parts of the region:
+            // border strips and interior are read, only the halo is written
+            const uint32_t e = t + 1, slot = exch_slot(e), tag = exch_tag(e);
+            tile_publish(lat, a.exch + (size_t)(slot * T + tile) * sd, G, tag);
+            // the tags replace flags: each halo word is awaited on its own; the
+            // counts run while the first halo loads are in flight
+            const uint32_t st = tile_gather(
+                lat, a.exch, HP, G, ty, tx, slot * T * sd, tag, a.abort,
+                a.spin_limit, [&] {
+                    if (a.counts) {
+                        if (kPacked)
+                            tile_count_sums(lat, G, S, s_part);
+                        else
+                            tile_count_wide(lat, G, S, s_cnt);
+                    }
+                });
+            if (st) {
+                if (st == 2) {
+                    xstore(a.abort, 1u);
+                    atomicOr(&g_async_error, 1u);
                 }
-            });
-        if (st) {
-            if (st == 2) {
-                xstore(a.abort, 1u);
-                atomicOr(&g_async_error, 1u);
+                s_misc[0] = 1;
             }
-            s_misc[0] = 1;
-        }
-        __syncthreads();
-        if (a.counts) {
-            uint32_t *row = a.counts + (size_t)(t + 1) * (S + 1);
-            if constexpr (kPacked) {
-                if (tid < 64) // one wave; the slots are next used 4 barriers on
-                    tile_count_flush(s_part, S, G.TH * G.TW, row);
-            } else if (tid <= S) {
-                atomicAdd(&row[tid], s_cnt[tid]);
-                s_cnt[tid] = 0;
+            __syncthreads();
+            if (a.counts) {
+                uint32_t *row = a.counts + (size_t)(t + 1) * (S + 1);
+                if constexpr (kPacked) {
+                    if (tid < 64) // one wave; the slots are next used 4 barriers on
+                        tile_count_flush(s_part, S, G.TH * G.TW, row);
+                } else if (tid <= S) {
+                    atomicAdd(&row[tid], s_cnt[tid]);
+                    s_cnt[tid] = 0;
+                }
+            }
+            if (s_misc[0]) {
+                aborted = true;
+                break;
             }
         }
-        if (s_misc[0]) {
-            aborted = true;
-            break;
-        }
+    };
+    if (a.list) {
+        const TileList TL = tile_list(G, ty, tx);
+        run([&](uint32_t t) {
+            tile_mcs_list(lat, G, TL, t, a.replica, k0, k1, qc);
+        });
+    } else {
+        run([&](uint32_t t) {
+            tile_mcs(lat, G, W, t, a.replica, k0, k1, qc);
+        });
     }
     if (!aborted)
         tile_store(lat, a.lattice, G, ty, tx);
@@ -1044,7 +1058,32 @@ struct TiledPlan {
     TileGeom G{};
     uint32_t threads = 0;
     size_t lds = 0;
+    bool list = false; // quads by TileList (persistent kernel only)
 };
+
+// Quad iterations of a pass (oy = 0) on the busiest SIMD, with waves dealt
+// to the four SIMDs of a CU in turn: a wave takes as many iterations as its
+// busiest lane.  Column walk (TileWalk) or row-major list (TileList).
+uint32_t walk_simd_load(const TileGeom &G, uint32_t nt, bool list)
+{
+    const uint32_t NJ = (G.TW + 16) >> 3, nbr = G.RH() >> 1;
+    const uint32_t nq = nbr * NJ, Lb = G.L >> 1;
+    const uint32_t rstep = std::min(nt / NJ, Lb);
+    uint32_t simd[4] = {0, 0, 0, 0};
+    for (uint32_t w = 0; w * 64 < nt; ++w) {
+        uint32_t it = 0;
+        for (uint32_t t = w * 64; t < std::min(nt, w * 64 + 64); ++t) {
+            uint32_t n = 0;
+            if (list)
+                n = t < nq ? (nq - t + nt - 1) / nt : 0;
+            else if (rstep && t / NJ < rstep)
+                n = (nbr - t / NJ + rstep - 1) / rstep;
+            it = std::max(it, n);
+        }
+        simd[w & 3] += it;
+    }
+    return std::max(std::max(simd[0], simd[1]), std::max(simd[2], simd[3]));
+}
 
 // Workgroup size for a tile (0: the tile is too wide): see tile_threads;
 // the counts walk one column of dword pairs per thread (tile_count_sums), so
@@ -1103,9 +1142,22 @@ TiledPlan plan_tiled_uncached(uint32_t L, uint32_t S)
             const size_t lds = G.region_bytes();
             if (lds + static_lds_bytes(S) + 64 > lds_max)
                 continue;
-            const uint32_t nt = tiled_threads(G, 1024);
+            uint32_t nt = tiled_threads(G, 1024);
             if (nt == 0)
                 continue;
+            // the balanced list walk where it lowers the busiest SIMD's load
+            bool list = false;
+            uint32_t load = walk_simd_load(G, nt, false);
+            for (uint32_t n = 1024; n >= 256; n -= 256) { // ties: more waves
+                if (!tile_list_fits(G, n) || G.TW / 4 > n)
+                    continue;
+                const uint32_t l = walk_simd_load(G, n, true);
+                if (l < load) {
+                    load = l;
+                    nt = n;
+                    list = true;
+                }
+            }
             const void *fn =
                 ESCG_KERNEL2(tiled_persistent_kernel, S <= 7, false);
             allow_dynamic_lds(fn, lds);
@@ -1123,6 +1175,7 @@ TiledPlan plan_tiled_uncached(uint32_t L, uint32_t S)
                 best.G = G;
                 best.threads = nt;
                 best.lds = lds;
+                best.list = list;
             }
         }
     }
@@ -1283,6 +1336,7 @@ escg_status run_tiled_persistent(const escg_params *p, const Derived &d,
     a.n_mcs = n_mcs;
     a.spin_limit = 1u << 22; // polls (seconds), then abort with an error
     a.moore = (p->flags & ESCG_FLAG_MOORE) ? 1u : 0u;
+    a.list = plan.list ? 1u : 0u;
     a.ab = d.d_ab;
     for (int i = 0; i < 32; ++i)
         a.dom[i] = p->dom[i];

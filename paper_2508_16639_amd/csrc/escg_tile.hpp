@@ -194,6 +194,85 @@ __device__ __forceinline__ void tile_mcs(uint8_t *lat, const TileGeom &G,
     }
 }
 
+// Balanced alternative to TileWalk when a pass has at most kListSlots *
+// blockDim quads: quad q = tid + i * blockDim (i < kListSlots) in row-major
+// order over (LDS block row, quad column), so every wave of the workgroup
+// gets the same number of quads up to one, and with 1024 threads the four
+// SIMDs of the CU get equal shares (a column walk leaves the SIMD that
+// holds one wave fewer idle for a quarter of each pass).  A thread keeps
+// the LDS offset (oy = 0) and the Philox counter word of each of its quads;
+// a pass with oy = 1 has one block row fewer and skips the quads of the
+// last row.
+constexpr uint32_t kListSlots = 3;
+
+struct TileList {
+    uint32_t pa[kListSlots];
+    uint32_t c0[kListSlots];
+};
+
+__host__ __device__ inline bool tile_list_fits(const TileGeom &G,
+                                               uint32_t threads)
+{
+    return (G.RH() >> 1) * ((G.TW + 16) >> 3) <= kListSlots * threads;
+}
+
+__device__ inline TileList tile_list(const TileGeom &G, uint32_t ty,
+                                     uint32_t tx)
+{
+    const uint32_t L = G.L, LS = G.LS(), Q = L >> 3, Lb = L >> 1;
+    const uint32_t NJ = (G.TW + 16) >> 3;
+    const uint32_t bx = (tx * G.TW) / 8 + Q - 1, by = (ty * G.TH) / 2 + Lb - 2;
+    TileList T;
+#pragma unroll
+    for (uint32_t i = 0; i < kListSlots; ++i) {
+        const uint32_t q = threadIdx.x + i * blockDim.x;
+        const uint32_t row = q / NJ, col = q - row * NJ;
+        T.pa[i] = 2 * row * LS + 8 * col;
+        T.c0[i] = ((by + row) % Lb) * Q + (bx + col) % Q;
+    }
+    return T;
+}
+
+template <class Ctx>
+__device__ __forceinline__ void tile_pass_list(uint8_t *lat,
+                                               const TileGeom &G,
+                                               const TileList &T, uint32_t w,
+                                               uint32_t p, uint32_t t,
+                                               uint32_t replica, uint32_t k0,
+                                               uint32_t k1, const Ctx &qc)
+{
+    const uint32_t LS = G.LS();
+    const uint32_t ox = w & 1u, oy = (w >> 1) & 1u;
+    const uint32_t nq = ((G.RH() - oy) >> 1) * ((G.TW + 16) >> 3);
+    const uint32_t ctr2 = (kTagPass << 8) | p, dy = oy * LS;
+#pragma unroll
+    for (uint32_t i = 0; i < kListSlots; ++i) {
+        if (threadIdx.x + i * blockDim.x < nq) {
+            const Words r = philox10(T.c0[i], t, ctr2, replica, k0, k1);
+            const uint32_t pa = T.pa[i] + dy;
+            if (ox == 0)
+                quad_even(lat, pa, pa + LS, r, qc);
+            else
+                quad_odd(lat, pa, pa + LS, pa + 8, pa + LS + 8, r, qc);
+        }
+    }
+}
+
+template <class Ctx>
+__device__ __forceinline__ void tile_mcs_list(uint8_t *lat, const TileGeom &G,
+                                              const TileList &T, uint32_t t,
+                                              uint32_t replica, uint32_t k0,
+                                              uint32_t k1, const Ctx &qc)
+{
+    const Words off = philox10(0u, t, kTagOffset << 8, replica, k0, k1);
+#pragma unroll
+    for (uint32_t p = 0; p < 4; ++p) {
+        tile_pass_list(lat, G, T, __builtin_amdgcn_readfirstlane(off.w[p]),
+                       p, t, replica, k0, k1, qc);
+        __syncthreads();
+    }
+}
+
 // Device-coherent word store / load for the exchange area: relaxed
 // agent-scope atomics compile to sc1 stores and loads, which are coherent
 // across XCDs without L2 writeback or invalidation.
