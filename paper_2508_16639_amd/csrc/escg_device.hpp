@@ -58,6 +58,17 @@ __device__ __forceinline__ uint32_t xor3_vvs(uint32_t a, uint32_t b,
     return r;
 }
 
+// A per-lane (vector register) copy of a wave-uniform value.  The gfx950
+// VALU reads at most one scalar operand per instruction, so a select between
+// two uniform constants otherwise needs a v_mov of one of them every time;
+// copies made once before a loop avoid that.
+__device__ __forceinline__ uint32_t vgpr_copy(uint32_t k)
+{
+    uint32_t r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(k));
+    return r;
+}
+
 // One Philox round: (c0, c1, c2, c3) with round key (k0, k1).
 #define ESCG_PHILOX_ROUND(X0, X1)                                             \
     do {                                                                      \

@@ -139,6 +139,8 @@ __device__ inline QuadCtxT<kProb> make_quad_ctx(const LdsTables<SP> &T,
     qc.B1 = a.a1 * tb;
     qc.B2 = a.a2 * tb;
     qc.B3 = a.a3 * tb;
+    qc.B2 = vgpr_copy(qc.B2); // the selects in block_update read B2, B3
+    qc.B3 = vgpr_copy(qc.B3); // as vector operands
     qc.dotw = (2u * SP) | (2u << 8);
     qc.ab = reinterpret_cast<const uint8_t *>(T.ab);
     qc.abw = (4u * SP) | (4u << 8);
