@@ -440,12 +440,13 @@ struct TiledArgs {
     uint64_t seed;
     TileGeom G;
     uint32_t S, T1, T2, replica, mcs0, n_mcs, spin_limit, moore;
-    uint32_t list;        // quads by TileList (else TileWalk)
     const uint32_t *ab;   // selection thresholds (global) or null
     uint32_t dom[32];
 };
 
-template <bool kPacked, bool kProb>
+// kList: the quads of a pass by TileList (else TileWalk); one walk per
+// instantiation keeps the other's code and registers out of the MCS loop.
+template <bool kPacked, bool kProb, bool kList>
 __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
 {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -472,63 +473,58 @@ __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
     tile_load(lat, a.lattice, G, ty, tx);
     setup_tables(TB, a.dom, a.moore != 0, kProb ? a.ab : nullptr);
     const auto qc = make_quad_ctx<kProb>(TB, a.T1, a.T2); // after a barrier
-    const TileWalk W = tile_walk(G, ty, tx);
     const HaloPlan HP = halo_plan(a.exch, G, ty, tx);
 
     bool aborted = false;
-    // the MCS loop, with the quad walk of the passes as a parameter
-    auto run = [&](auto &&mcs) {
-        for (uint32_t t = 0; t < a.n_mcs; ++t) {
-            mcs(a.mcs0 + t);
-            // publish, count and gather touch disjoint parts of the region:
-            // border strips and interior are read, only the halo is written
-            const uint32_t e = t + 1, slot = exch_slot(e), tag = exch_tag(e);
-            tile_publish(lat, a.exch + (size_t)(slot * T + tile) * sd, G, tag);
-            // the tags replace flags: each halo word is awaited on its own; the
-            // counts run while the first halo loads are in flight
-            const uint32_t st = tile_gather(
-                lat, a.exch, HP, G, ty, tx, slot * T * sd, tag, a.abort,
-                a.spin_limit, [&] {
-                    if (a.counts) {
-                        if (kPacked)
-                            tile_count_sums(lat, G, S, s_part);
-                        else
-                            tile_count_wide(lat, G, S, s_cnt);
-                    }
-                });
-            if (st) {
-                if (st == 2) {
-                    xstore(a.abort, 1u);
-                    atomicOr(&g_async_error, 1u);
+    const TileWalk W = tile_walk(G, ty, tx);
+    TileList TL;
+    if constexpr (kList)
+        TL = tile_list(G, ty, tx);
+    // (a plain loop: the same loop written as a lambda taking the walk
+    // measured 10 % slower per MCS on mid-size lattices)
+    for (uint32_t t = 0; t < a.n_mcs; ++t) {
+        if constexpr (kList)
+            tile_mcs_list(lat, G, TL, a.mcs0 + t, a.replica, k0, k1, qc);
+        else
+            tile_mcs(lat, G, W, a.mcs0 + t, a.replica, k0, k1, qc);
+        // publish, count and gather touch disjoint parts of the region:
+        // border strips and interior are read, only the halo is written
+        const uint32_t e = t + 1, slot = exch_slot(e), tag = exch_tag(e);
+        tile_publish(lat, a.exch + (size_t)(slot * T + tile) * sd, G, tag);
+        // the tags replace flags: each halo word is awaited on its own; the
+        // counts run while the first halo loads are in flight
+        const uint32_t st = tile_gather(
+            lat, a.exch, HP, G, ty, tx, slot * T * sd, tag, a.abort,
+            a.spin_limit, [&] {
+                if (a.counts) {
+                    if (kPacked)
+                        tile_count_sums(lat, G, S, s_part);
+                    else
+                        tile_count_wide(lat, G, S, s_cnt);
                 }
-                s_misc[0] = 1;
+            });
+        if (st) {
+            if (st == 2) {
+                xstore(a.abort, 1u);
+                atomicOr(&g_async_error, 1u);
             }
-            __syncthreads();
-            if (a.counts) {
-                uint32_t *row = a.counts + (size_t)(t + 1) * (S + 1);
-                if constexpr (kPacked) {
-                    if (tid < 64) // one wave; the slots are next used 4 barriers on
-                        tile_count_flush(s_part, S, G.TH * G.TW, row);
-                } else if (tid <= S) {
-                    atomicAdd(&row[tid], s_cnt[tid]);
-                    s_cnt[tid] = 0;
-                }
-            }
-            if (s_misc[0]) {
-                aborted = true;
-                break;
+            s_misc[0] = 1;
+        }
+        __syncthreads();
+        if (a.counts) {
+            uint32_t *row = a.counts + (size_t)(t + 1) * (S + 1);
+            if constexpr (kPacked) {
+                if (tid < 64) // one wave; the slots are next used 4 barriers on
+                    tile_count_flush(s_part, S, G.TH * G.TW, row);
+            } else if (tid <= S) {
+                atomicAdd(&row[tid], s_cnt[tid]);
+                s_cnt[tid] = 0;
             }
         }
-    };
-    if (a.list) {
-        const TileList TL = tile_list(G, ty, tx);
-        run([&](uint32_t t) {
-            tile_mcs_list(lat, G, TL, t, a.replica, k0, k1, qc);
-        });
-    } else {
-        run([&](uint32_t t) {
-            tile_mcs(lat, G, W, t, a.replica, k0, k1, qc);
-        });
+        if (s_misc[0]) {
+            aborted = true;
+            break;
+        }
     }
     if (!aborted)
         tile_store(lat, a.lattice, G, ty, tx);
@@ -975,6 +971,21 @@ uint32_t lds_threads(uint32_t Lmax) { return Lmax <= 128 ? 256u : 512u; }
               : ((prob) ? (const void *)K<false, true>                        \
                         : (const void *)K<false, false>))
 
+// The persistent kernel for (S <= 7, dominance probabilities, list walk).
+const void *persistent_kernel(bool packed, bool prob, bool list)
+{
+    static const void *const fns[8] = {
+        (const void *)tiled_persistent_kernel<false, false, false>,
+        (const void *)tiled_persistent_kernel<false, false, true>,
+        (const void *)tiled_persistent_kernel<false, true, false>,
+        (const void *)tiled_persistent_kernel<false, true, true>,
+        (const void *)tiled_persistent_kernel<true, false, false>,
+        (const void *)tiled_persistent_kernel<true, false, true>,
+        (const void *)tiled_persistent_kernel<true, true, false>,
+        (const void *)tiled_persistent_kernel<true, true, true>};
+    return fns[(packed ? 4 : 0) | (prob ? 2 : 0) | (list ? 1 : 0)];
+}
+
 escg_status launch_lds_single(const JobDev &J, bool small, uint8_t *base,
                               hipStream_t st)
 {
@@ -1158,8 +1169,7 @@ TiledPlan plan_tiled_uncached(uint32_t L, uint32_t S)
                     list = true;
                 }
             }
-            const void *fn =
-                ESCG_KERNEL2(tiled_persistent_kernel, S <= 7, false);
+            const void *fn = persistent_kernel(S <= 7, false, list);
             allow_dynamic_lds(fn, lds);
             int per_cu = 0;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nt,
@@ -1336,7 +1346,6 @@ escg_status run_tiled_persistent(const escg_params *p, const Derived &d,
     a.n_mcs = n_mcs;
     a.spin_limit = 1u << 22; // polls (seconds), then abort with an error
     a.moore = (p->flags & ESCG_FLAG_MOORE) ? 1u : 0u;
-    a.list = plan.list ? 1u : 0u;
     a.ab = d.d_ab;
     for (int i = 0; i < 32; ++i)
         a.dom[i] = p->dom[i];
@@ -1347,7 +1356,7 @@ escg_status run_tiled_persistent(const escg_params *p, const Derived &d,
     if (counts)
         launch_fill(counts + (p->S + 1), (size_t)n_mcs * (p->S + 1), 0, st);
     void *args[] = {&a};
-    const void *fn = ESCG_KERNEL2(tiled_persistent_kernel, d.small, d.prob);
+    const void *fn = persistent_kernel(d.small, d.prob, plan.list);
     allow_dynamic_lds(fn, plan.lds);
     hipError_t e = hipLaunchCooperativeKernel(fn, dim3(T), dim3(plan.threads),
                                               args, (unsigned)plan.lds, st);
