@@ -38,7 +38,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-VALU_PEAK_TLANEOPS = 39.32     # 256 CU * 4 SIMD * 16 lanes * 2.4 GHz, VALU issue
+VALU_PEAK_TLANEOPS = 39.32     # 256 CU * 4 SIMD * 16 lanes * 2.4 GHz, int32 VALU
 BYTES_PER_SU = 2.0             # read + write of one uint8 site per update
 
 
@@ -295,16 +295,16 @@ def main():
     prof = recorded_profile("counters_rpsls_L3200.json")
     traffic = prof.get("hbm_bytes_per_launch") if prof else None
     alu = None
-    if prof and prof.get("valu_issue_slots_per_launch"):
-        # VALU issue slots (wave64 instructions, 64-bit integer ones twice:
-        # they issue at half rate) x 64 lanes per kernel second
-        a = 64 * prof["valu_issue_slots_per_launch"] / (h["kernel_ms"] * 1e-3) / 1e12
+    if prof and prof.get("valu_lane_ops_per_launch"):
+        # wave64 VALU instructions x 64 lanes per kernel second (every
+        # integer VALU instruction the kernel uses issues at full rate,
+        # v_mad_u64_u32 included: paper_2508_16639_amd/valu_rates.hip)
+        a = prof["valu_lane_ops_per_launch"] / (h["kernel_ms"] * 1e-3) / 1e12
         alu = {"bound": "alu", "achieved": a, "peak": VALU_PEAK_TLANEOPS,
-               "unit": "T lane-slots/s", "frac": a / VALU_PEAK_TLANEOPS,
-               "note": "VALU issue slots from SQ_INSTS_VALU + "
-                       "SQ_INSTS_VALU_INT64 (profiles/counters_rpsls_L3200"
-                       ".json) over the live kernel time; peak 256 CU x 4 "
-                       "SIMD x 16 lanes x 2.4 GHz"}
+               "unit": "T lane-instr/s", "frac": a / VALU_PEAK_TLANEOPS,
+               "note": "SQ_INSTS_VALU x 64 per launch (profiles/counters_"
+                       "rpsls_L3200.json) over the live kernel time; peak "
+                       "256 CU x 4 SIMD x 16 lanes x 2.4 GHz"}
     out = {
         "metric": "site-updates/s at L=3200 (RPSLS, 1000 MCS, counts every "
                   "MCS) + replica-jobs/s with p50/p99 latency vs plain",
