@@ -117,6 +117,107 @@ __device__ __forceinline__ void count_dwords(const uint32_t *lat32,
     }
 }
 
+// Whole-lattice counts for S <= 7 from the linear sums of tile_count_sums:
+// every thread walks the dword pairs i = tid, tid + blockDim, ... of the LDS
+// lattice (padding bytes, value 12, get code 0 and add 12 each to the value
+// sum, which the caller takes off) in groups of at most 7 pairs, and adds
+// its NS - 1 sums to part[q * 8 + (lane & 7)] with LDS atomics.  The slots
+// are cleared once per job and then accumulate: each MCS's sums are the
+// differences of two cumulative totals (exact modulo 2^32).
+template <int NS>
+__device__ __forceinline__ void lds_count_sums(const uint32_t *lat32,
+                                               uint32_t ndw, uint32_t *part)
+{
+    constexpr int NP = (NS - 2) / 2;
+    const uint2 *lat64 = reinterpret_cast<const uint2 *>(lat32);
+    const uint32_t np = ndw >> 1, nt = blockDim.x; // ndw is even
+    uint32_t n[NS - 1];
+#pragma unroll
+    for (int q = 0; q < NS - 1; ++q)
+        n[q] = 0;
+    uint32_t i = threadIdx.x;
+    while (i < np) {
+        uint32_t sv = 0, cp[NP];
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+            cp[k] = 0;
+        for (uint32_t g = 0; g < 7 && i < np; ++g, i += nt) {
+            const uint2 v = lat64[i];
+            sv += v.x + v.y;
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                const uint64_t t = pair_code_table(k);
+                const uint32_t hi = (uint32_t)(t >> 32), lo = (uint32_t)t;
+                cp[k] += __builtin_amdgcn_perm(hi, lo, v.x) +
+                         __builtin_amdgcn_perm(hi, lo, v.y);
+            }
+        }
+        n[NS - 2] = __builtin_amdgcn_udot4(sv, 0x01010101u, n[NS - 2], false);
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            n[2 * k] = __builtin_amdgcn_udot8(cp[k], 0x01010101u, n[2 * k],
+                                              false);
+            n[2 * k + 1] = __builtin_amdgcn_udot8(cp[k], 0x10101010u,
+                                                  n[2 * k + 1], false);
+        }
+    }
+    uint32_t *slot = part + (threadIdx.x & 7u);
+#pragma unroll
+    for (int q = 0; q < NS - 1; ++q)
+        atomicAdd(slot + 8 * q, n[q]);
+}
+
+// One MCS's counts c[0..7] (uniform; c[s] = 0 for s >= NS) after a barrier
+// that follows lds_count_sums: every wave adds the eight slots of each sum
+// (DPP quad swaps and row_shr:4, total in lane 8q+4), takes the previous
+// cumulative totals `prev` off and derives the species counts.
+template <int NS>
+__device__ __forceinline__ void lds_count_close(const uint32_t *part,
+                                                uint32_t (&prev)[7],
+                                                uint32_t sites, uint32_t pads,
+                                                uint32_t (&c)[8])
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t v = lane < 8u * (NS - 1) ? part[lane] : 0u;
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, true);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, true);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);
+    uint32_t D[NS - 1];
+#pragma unroll
+    for (int q = 0; q < NS - 1; ++q) {
+        const uint32_t T = (uint32_t)__builtin_amdgcn_readlane((int)v, 8 * q + 4);
+        D[q] = T - prev[q];
+        prev[q] = T;
+    }
+    D[NS - 2] -= 12u * pads; // padding bytes in the value sum
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+        c[s] = s < NS ? count_species<NS>((uint32_t)s, D, sites) : 0u;
+}
+
+// c[k] for a per-lane index k <= 7 (c uniform).
+__device__ __forceinline__ uint32_t pick8(const uint32_t (&c)[8], uint32_t k)
+{
+    uint32_t v = c[0];
+#pragma unroll
+    for (uint32_t s = 1; s < 8; ++s)
+        v = (k == s) ? c[s] : v;
+    return v;
+}
+
+// stop_met on uniform counts c[0..7] (S <= 7), without indexing by S.
+__device__ __forceinline__ bool stop_met8(const uint32_t (&c)[8], uint32_t S,
+                                          uint32_t mode)
+{
+    if (mode == ESCG_STOP_NONE)
+        return false;
+    uint32_t alive = 0;
+#pragma unroll
+    for (uint32_t s = 1; s < 8; ++s)
+        alive += (s <= S && c[s] > 0u) ? 1u : 0u;
+    return mode == ESCG_STOP_FIRST_EXTINCTION ? alive < S : alive <= 1u;
+}
+
 template <bool kPacked, bool kProb>
 __device__ void run_job_lds(const JobDev &J, uint8_t *base, uint8_t *smem,
                             LdsTables<kPacked ? 8 : 32> &TB)
@@ -161,36 +262,78 @@ __device__ void run_job_lds(const JobDev &J, uint8_t *base, uint8_t *smem,
             reinterpret_cast<uint16_t *>(lat)[(r * LS >> 1) + c] = g16[i];
         }
     }
+    if (kPacked)
+        for (uint32_t i = tid; i < 64; i += nt)
+            s_cnt[i] = 0; // count slots (lds_count_sums), cleared per job
     __syncthreads();
     const auto qc = make_quad_ctx<kProb>(TB, J.T1, J.T2);
     const LdsWalk W = lds_walk(L, LS);
     const uint32_t ndw = (LS * L) >> 2;
 
+    // counts of the current state: S <= 7 into c[] (uniform, every wave),
+    // else into the LDS row `row` of s_cnt; returns the stop test
+    uint32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint32_t prev[7] = {0, 0, 0, 0, 0, 0, 0};
+    const uint32_t sites = L * L, pads = (LS - L) * L;
+    const uint32_t ns = count_states(S);
     uint32_t cur = 0;
-    if (kPacked)
-        count_dwords<8>(lat32, ndw, S, s_cnt);
-    else
+    bool stop;
+    if constexpr (kPacked) {
+        if (ns == 4) {
+            lds_count_sums<4>(lat32, ndw, s_cnt);
+            __syncthreads();
+            lds_count_close<4>(s_cnt, prev, sites, pads, c);
+        } else if (ns == 6) {
+            lds_count_sums<6>(lat32, ndw, s_cnt);
+            __syncthreads();
+            lds_count_close<6>(s_cnt, prev, sites, pads, c);
+        } else {
+            lds_count_sums<8>(lat32, ndw, s_cnt);
+            __syncthreads();
+            lds_count_close<8>(s_cnt, prev, sites, pads, c);
+        }
+        stop = stop_met8(c, S, J.mode);
+        if (J.counts && tid <= S)
+            J.counts[tid] = pick8(c, tid);
+    } else {
         count_dwords<32>(lat32, ndw, S, s_cnt);
-    __syncthreads();
-    bool stop = stop_met(s_cnt, S, J.mode);
-    if (J.counts && tid <= S)
-        J.counts[tid] = s_cnt[tid];
+        __syncthreads();
+        stop = stop_met(s_cnt, S, J.mode);
+        if (J.counts && tid <= S)
+            J.counts[tid] = s_cnt[tid];
+    }
     uint32_t t = 0;
     while (!stop && t < J.max_mcs) {
         const uint32_t nxt = cur ^ 1u;
-        if (tid < 32)
+        if (!kPacked && tid < 32)
             s_cnt[nxt * 32 + tid] = 0;
         lds_mcs(lat, L, LS, J.mcs0 + t, J.replica, k0, k1, qc, W);
-        if (kPacked)
-            count_dwords<8>(lat32, ndw, S, s_cnt + nxt * 32);
-        else
-            count_dwords<32>(lat32, ndw, S, s_cnt + nxt * 32);
-        __syncthreads();
-        cur = nxt;
         ++t;
-        stop = stop_met(s_cnt + cur * 32, S, J.mode);
-        if (J.counts && tid <= S)
-            J.counts[(size_t)t * (S + 1) + tid] = s_cnt[cur * 32 + tid];
+        if constexpr (kPacked) {
+            if (ns == 4) {
+                lds_count_sums<4>(lat32, ndw, s_cnt);
+                __syncthreads();
+                lds_count_close<4>(s_cnt, prev, sites, pads, c);
+            } else if (ns == 6) {
+                lds_count_sums<6>(lat32, ndw, s_cnt);
+                __syncthreads();
+                lds_count_close<6>(s_cnt, prev, sites, pads, c);
+            } else {
+                lds_count_sums<8>(lat32, ndw, s_cnt);
+                __syncthreads();
+                lds_count_close<8>(s_cnt, prev, sites, pads, c);
+            }
+            stop = stop_met8(c, S, J.mode);
+            if (J.counts && tid <= S)
+                J.counts[(size_t)t * (S + 1) + tid] = pick8(c, tid);
+        } else {
+            count_dwords<32>(lat32, ndw, S, s_cnt + nxt * 32);
+            __syncthreads();
+            cur = nxt;
+            stop = stop_met(s_cnt + cur * 32, S, J.mode);
+            if (J.counts && tid <= S)
+                J.counts[(size_t)t * (S + 1) + tid] = s_cnt[cur * 32 + tid];
+        }
     }
     if ((L & 3u) == 0) {
         const uint32_t dwr = L >> 2, nw = L * dwr;
@@ -215,7 +358,7 @@ __device__ void run_job_lds(const JobDev &J, uint8_t *base, uint8_t *smem,
             else if (i == 1)
                 v = t;
             else if (i - 2 <= S)
-                v = s_cnt[cur * 32 + (i - 2)];
+                v = kPacked ? pick8(c, i - 2) : s_cnt[cur * 32 + (i - 2)];
             J.result[i] = v;
         }
     }
@@ -891,6 +1034,12 @@ size_t static_lds_bytes(uint32_t S)
     return S <= 7 ? sizeof(LdsTables<8>) : sizeof(LdsTables<32>);
 }
 
+// The tiled kernels add the count slots (tile_count_sums) to the tables.
+size_t tiled_static_lds_bytes(uint32_t S)
+{
+    return static_lds_bytes(S) + sizeof(uint32_t) * 8 * kCountSlots;
+}
+
 size_t lds_job_bytes(uint32_t L, uint32_t /*S*/)
 {
     return (size_t)row_stride(L) * L;
@@ -1151,7 +1300,7 @@ TiledPlan plan_tiled_uncached(uint32_t L, uint32_t S)
             TileGeom G{L, TH, TW, L / TH, L / TW};
             const uint32_t T = G.TY * G.TX;
             const size_t lds = G.region_bytes();
-            if (lds + static_lds_bytes(S) + 64 > lds_max)
+            if (lds + tiled_static_lds_bytes(S) + 64 > lds_max)
                 continue;
             uint32_t nt = tiled_threads(G, 1024);
             if (nt == 0)
@@ -1238,7 +1387,7 @@ TiledPlan plan_step_uncached(uint32_t L, uint32_t S)
                 continue;
             TileGeom G{L, TH, TW, L / TH, L / TW};
             const size_t lds = G.region_bytes();
-            if (lds + static_lds_bytes(S) + 64 > lds_max)
+            if (lds + tiled_static_lds_bytes(S) + 64 > lds_max)
                 continue;
             if (tiled_threads(G, 512) == 0)
                 continue;
