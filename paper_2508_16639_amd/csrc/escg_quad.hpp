@@ -238,6 +238,50 @@ __device__ __forceinline__ void quad_odd(uint8_t *lat, uint32_t pa,
     lat[ec] = (uint8_t)(c1 >> 24);
 }
 
+// Load and store halves of quad_even / quad_odd (ox = 0 / 1, uniform), for
+// callers that keep the next quad's rows in flight while updating one:
+// pa is the aligned LDS offset of the top row, the bottom row is LS further.
+struct QuadRows {
+    uint32_t a0, a1, c0, c1;
+};
+
+__device__ __forceinline__ QuadRows quad_load(const uint8_t *lat, uint32_t pa,
+                                              uint32_t LS, uint32_t ox)
+{
+    const uint2 ra = *reinterpret_cast<const uint2 *>(lat + pa);
+    const uint2 rc = *reinterpret_cast<const uint2 *>(lat + pa + LS);
+    if (ox == 0)
+        return QuadRows{ra.x, ra.y, rc.x, rc.y};
+    const uint32_t xa = lat[pa + 8], xc = lat[pa + LS + 8];
+    return QuadRows{__builtin_amdgcn_alignbyte(ra.y, ra.x, 1),
+                    __builtin_amdgcn_alignbyte(xa, ra.y, 1),
+                    __builtin_amdgcn_alignbyte(rc.y, rc.x, 1),
+                    __builtin_amdgcn_alignbyte(xc, rc.y, 1)};
+}
+
+__device__ __forceinline__ void quad_store(uint8_t *lat, uint32_t pa,
+                                           uint32_t LS, uint32_t ox,
+                                           const QuadRows &q)
+{
+    const uint32_t pc = pa + LS;
+    if (ox == 0) {
+        *reinterpret_cast<uint2 *>(lat + pa) = make_uint2(q.a0, q.a1);
+        *reinterpret_cast<uint2 *>(lat + pc) = make_uint2(q.c0, q.c1);
+        return;
+    }
+    // bytes 1..8 of the window: b8 at +1, b16 at +2, b32 at +4, b8 at +8
+    lat[pa + 1] = (uint8_t)q.a0;
+    *reinterpret_cast<uint16_t *>(lat + pa + 2) = (uint16_t)(q.a0 >> 8);
+    *reinterpret_cast<uint32_t *>(lat + pa + 4) =
+        __builtin_amdgcn_alignbyte(q.a1, q.a0, 3);
+    lat[pa + 8] = (uint8_t)(q.a1 >> 24);
+    lat[pc + 1] = (uint8_t)q.c0;
+    *reinterpret_cast<uint16_t *>(lat + pc + 2) = (uint16_t)(q.c0 >> 8);
+    *reinterpret_cast<uint32_t *>(lat + pc + 4) =
+        __builtin_amdgcn_alignbyte(q.c1, q.c0, 3);
+    lat[pc + 8] = (uint8_t)(q.c1 >> 24);
+}
+
 // One block addressed site by site (irregular quads: lattice edges with
 // wrap inside the quad, or blocks past the row end).
 template <class Ctx>

@@ -233,6 +233,9 @@ __device__ inline TileList tile_list(const TileGeom &G, uint32_t ty,
     return T;
 }
 
+// The quads of slot i + 1 are loaded before slot i is updated (they lie in
+// other block rows, so the order is free), which keeps an LDS read in flight
+// across each update.
 template <class Ctx>
 __device__ __forceinline__ void tile_pass_list(uint8_t *lat,
                                                const TileGeom &G,
@@ -245,15 +248,21 @@ __device__ __forceinline__ void tile_pass_list(uint8_t *lat,
     const uint32_t ox = w & 1u, oy = (w >> 1) & 1u;
     const uint32_t nq = ((G.RH() - oy) >> 1) * ((G.TW + 16) >> 3);
     const uint32_t ctr2 = (kTagPass << 8) | p, dy = oy * LS;
+    bool v[kListSlots];
+    QuadRows q[kListSlots];
+#pragma unroll
+    for (uint32_t i = 0; i < kListSlots; ++i)
+        v[i] = threadIdx.x + i * blockDim.x < nq;
+    if (v[0])
+        q[0] = quad_load(lat, T.pa[0] + dy, LS, ox);
 #pragma unroll
     for (uint32_t i = 0; i < kListSlots; ++i) {
-        if (threadIdx.x + i * blockDim.x < nq) {
+        if (i + 1 < kListSlots && v[i + 1])
+            q[i + 1] = quad_load(lat, T.pa[i + 1] + dy, LS, ox);
+        if (v[i]) {
             const Words r = philox10(T.c0[i], t, ctr2, replica, k0, k1);
-            const uint32_t pa = T.pa[i] + dy;
-            if (ox == 0)
-                quad_even(lat, pa, pa + LS, r, qc);
-            else
-                quad_odd(lat, pa, pa + LS, pa + 8, pa + LS + 8, r, qc);
+            quad_update(q[i].a0, q[i].a1, q[i].c0, q[i].c1, r, qc);
+            quad_store(lat, T.pa[i] + dy, LS, ox, q[i]);
         }
     }
 }
