@@ -145,12 +145,13 @@ __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo,
     return __builtin_amdgcn_perm(hi, lo, sel);
 }
 
-// One block: B = [A, B, C, D] -> updated dword.
+// One block: B = [A, B, C, D] -> updated dword, given the block's selector
+// pair s = sel[w & 0xFF] (loaded by the caller, so that the lookups of a
+// quad can be issued early).
 template <class Ctx>
-__device__ __forceinline__ uint32_t block_update(uint32_t B, uint32_t w,
-                                                 const Ctx &c)
+__device__ __forceinline__ uint32_t block_update_sel(uint32_t B, uint32_t w,
+                                                     uint2 s, const Ctx &c)
 {
-    const uint2 s = c.sel[w & 0xFFu];
     const uint32_t xy = perm(B, B, s.x);
     // select values, not lvalues (an lvalue ?: selects addresses and keeps
     // the context in scratch memory)
@@ -172,27 +173,61 @@ __device__ __forceinline__ uint32_t block_update(uint32_t B, uint32_t w,
     return perm(out, B, s.y);
 }
 
-// Row segments (8 bytes each, little-endian: byte k = column k of the
-// segment) -> four updated segments in place.
 template <class Ctx>
-__device__ __forceinline__ void quad_update(uint32_t &a0, uint32_t &a1,
-                                            uint32_t &c0, uint32_t &c1,
-                                            const Words &w, const Ctx &c)
+__device__ __forceinline__ uint32_t block_update(uint32_t B, uint32_t w,
+                                                 const Ctx &c)
+{
+    return block_update_sel(B, w, c.sel[w & 0xFFu], c);
+}
+
+// The four selector pairs of a quad's words.
+struct QuadSel {
+    uint2 s[4];
+};
+
+template <class Ctx>
+__device__ __forceinline__ QuadSel quad_sel(const Words &w, const Ctx &c)
+{
+    QuadSel q;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        q.s[k] = c.sel[w.w[k] & 0xFFu];
+    return q;
+}
+
+// Row segments (8 bytes each, little-endian: byte k = column k of the
+// segment) -> four updated segments in place, with the selector pairs
+// already loaded.
+template <class Ctx>
+__device__ __forceinline__ void quad_update_sel(uint32_t &a0, uint32_t &a1,
+                                                uint32_t &c0, uint32_t &c1,
+                                                const Words &w,
+                                                const QuadSel &qs,
+                                                const Ctx &c)
 {
     // transpose: block j = [a(2j), a(2j+1), c(2j), c(2j+1)]
     uint32_t b0 = perm(a0, c0, 0x01000504u);
     uint32_t b1 = perm(a0, c0, 0x03020706u);
     uint32_t b2 = perm(a1, c1, 0x01000504u);
     uint32_t b3 = perm(a1, c1, 0x03020706u);
-    b0 = block_update(b0, w.w[0], c);
-    b1 = block_update(b1, w.w[1], c);
-    b2 = block_update(b2, w.w[2], c);
-    b3 = block_update(b3, w.w[3], c);
+    b0 = block_update_sel(b0, w.w[0], qs.s[0], c);
+    b1 = block_update_sel(b1, w.w[1], qs.s[1], c);
+    b2 = block_update_sel(b2, w.w[2], qs.s[2], c);
+    b3 = block_update_sel(b3, w.w[3], qs.s[3], c);
     // back to rows
     a0 = perm(b1, b0, 0x05040100u);
     c0 = perm(b1, b0, 0x07060302u);
     a1 = perm(b3, b2, 0x05040100u);
     c1 = perm(b3, b2, 0x07060302u);
+}
+
+// The same, looking the selector pairs up itself.
+template <class Ctx>
+__device__ __forceinline__ void quad_update(uint32_t &a0, uint32_t &a1,
+                                            uint32_t &c0, uint32_t &c1,
+                                            const Words &w, const Ctx &c)
+{
+    quad_update_sel(a0, a1, c0, c1, w, quad_sel(w, c), c);
 }
 
 // Quad whose columns start 8-byte aligned in LDS (offset ox = 0).

@@ -233,9 +233,9 @@ __device__ inline TileList tile_list(const TileGeom &G, uint32_t ty,
     return T;
 }
 
-// The quads of slot i + 1 are loaded before slot i is updated (they lie in
-// other block rows, so the order is free), which keeps an LDS read in flight
-// across each update.
+// The rows, Philox words and selector pairs of slot i + 1 are loaded before
+// slot i is updated (its quads lie in other block rows, so the order is
+// free), which keeps LDS reads in flight across each update.
 template <class Ctx>
 __device__ __forceinline__ void tile_pass_list(uint8_t *lat,
                                                const TileGeom &G,
@@ -250,18 +250,26 @@ __device__ __forceinline__ void tile_pass_list(uint8_t *lat,
     const uint32_t ctr2 = (kTagPass << 8) | p, dy = oy * LS;
     bool v[kListSlots];
     QuadRows q[kListSlots];
+    Words r[kListSlots];
+    QuadSel qs[kListSlots];
 #pragma unroll
     for (uint32_t i = 0; i < kListSlots; ++i)
         v[i] = threadIdx.x + i * blockDim.x < nq;
-    if (v[0])
+    if (v[0]) {
         q[0] = quad_load(lat, T.pa[0] + dy, LS, ox);
+        r[0] = philox10(T.c0[0], t, ctr2, replica, k0, k1);
+        qs[0] = quad_sel(r[0], qc);
+    }
 #pragma unroll
     for (uint32_t i = 0; i < kListSlots; ++i) {
-        if (i + 1 < kListSlots && v[i + 1])
+        if (i + 1 < kListSlots && v[i + 1]) {
             q[i + 1] = quad_load(lat, T.pa[i + 1] + dy, LS, ox);
+            r[i + 1] = philox10(T.c0[i + 1], t, ctr2, replica, k0, k1);
+            qs[i + 1] = quad_sel(r[i + 1], qc);
+        }
         if (v[i]) {
-            const Words r = philox10(T.c0[i], t, ctr2, replica, k0, k1);
-            quad_update(q[i].a0, q[i].a1, q[i].c0, q[i].c1, r, qc);
+            quad_update_sel(q[i].a0, q[i].a1, q[i].c0, q[i].c1, r[i], qs[i],
+                            qc);
             quad_store(lat, T.pa[i] + dy, LS, ox, q[i]);
         }
     }
