@@ -233,9 +233,10 @@ __device__ inline TileList tile_list(const TileGeom &G, uint32_t ty,
     return T;
 }
 
-// The rows, Philox words and selector pairs of slot i + 1 are loaded before
-// slot i is updated (its quads lie in other block rows, so the order is
-// free), which keeps LDS reads in flight across each update.
+// The Philox words and selector pairs of slot i + 1 are computed and loaded
+// before slot i is updated, so the selector lookups are in flight during
+// the update (prefetching the rows too measured no faster and needs more
+// registers than the 1024-thread launch allows without spills).
 template <class Ctx>
 __device__ __forceinline__ void tile_pass_list(uint8_t *lat,
                                                const TileGeom &G,
@@ -256,14 +257,14 @@ __device__ __forceinline__ void tile_pass_list(uint8_t *lat,
     for (uint32_t i = 0; i < kListSlots; ++i)
         v[i] = threadIdx.x + i * blockDim.x < nq;
     if (v[0]) {
-        q[0] = quad_load(lat, T.pa[0] + dy, LS, ox);
         r[0] = philox10(T.c0[0], t, ctr2, replica, k0, k1);
         qs[0] = quad_sel(r[0], qc);
     }
 #pragma unroll
     for (uint32_t i = 0; i < kListSlots; ++i) {
+        if (v[i])
+            q[i] = quad_load(lat, T.pa[i] + dy, LS, ox);
         if (i + 1 < kListSlots && v[i + 1]) {
-            q[i + 1] = quad_load(lat, T.pa[i + 1] + dy, LS, ox);
             r[i + 1] = philox10(T.c0[i + 1], t, ctr2, replica, k0, k1);
             qs[i + 1] = quad_sel(r[i + 1], qc);
         }
