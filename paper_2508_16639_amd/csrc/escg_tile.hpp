@@ -236,14 +236,18 @@ __device__ inline TileList tile_list(const TileGeom &G, uint32_t ty,
 // The Philox words and selector pairs of slot i + 1 are computed and loaded
 // before slot i is updated, so the selector lookups are in flight during
 // the update (prefetching the rows too measured no faster and needs more
-// registers than the 1024-thread launch allows without spills).
+// registers than the 1024-thread launch allows without spills).  Those of
+// slot 0 arrive in (rf, sf), and the pass leaves the next pass's there
+// before its barrier (the selector table is constant, the words depend on
+// the counter only).
 template <class Ctx>
 __device__ __forceinline__ void tile_pass_list(uint8_t *lat,
                                                const TileGeom &G,
                                                const TileList &T, uint32_t w,
                                                uint32_t p, uint32_t t,
                                                uint32_t replica, uint32_t k0,
-                                               uint32_t k1, const Ctx &qc)
+                                               uint32_t k1, const Ctx &qc,
+                                               Words &rf, QuadSel &sf)
 {
     const uint32_t LS = G.LS();
     const uint32_t ox = w & 1u, oy = (w >> 1) & 1u;
@@ -256,10 +260,8 @@ __device__ __forceinline__ void tile_pass_list(uint8_t *lat,
 #pragma unroll
     for (uint32_t i = 0; i < kListSlots; ++i)
         v[i] = threadIdx.x + i * blockDim.x < nq;
-    if (v[0]) {
-        r[0] = philox10(T.c0[0], t, ctr2, replica, k0, k1);
-        qs[0] = quad_sel(r[0], qc);
-    }
+    r[0] = rf;
+    qs[0] = sf;
 #pragma unroll
     for (uint32_t i = 0; i < kListSlots; ++i) {
         if (v[i])
@@ -274,6 +276,10 @@ __device__ __forceinline__ void tile_pass_list(uint8_t *lat,
             quad_store(lat, T.pa[i] + dy, LS, ox, q[i]);
         }
     }
+    if (p < 3) { // the next pass's first slot, before the barrier
+        rf = philox10(T.c0[0], t, (kTagPass << 8) | (p + 1), replica, k0, k1);
+        sf = quad_sel(rf, qc);
+    }
 }
 
 template <class Ctx>
@@ -283,10 +289,12 @@ __device__ __forceinline__ void tile_mcs_list(uint8_t *lat, const TileGeom &G,
                                               uint32_t k1, const Ctx &qc)
 {
     const Words off = philox10(0u, t, kTagOffset << 8, replica, k0, k1);
+    Words rf = philox10(T.c0[0], t, kTagPass << 8, replica, k0, k1);
+    QuadSel sf = quad_sel(rf, qc); // slot 0 of pass 0
 #pragma unroll
     for (uint32_t p = 0; p < 4; ++p) {
         tile_pass_list(lat, G, T, __builtin_amdgcn_readfirstlane(off.w[p]),
-                       p, t, replica, k0, k1, qc);
+                       p, t, replica, k0, k1, qc, rf, sf);
         __syncthreads();
     }
 }

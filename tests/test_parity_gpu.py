@@ -482,3 +482,23 @@ def test_tile_shape_rejects_invalid():
         escg.set_tile_shape(3200, 100, 100)   # TW % 8 != 0
     with pytest.raises(escg.EscgError):
         escg.set_tile_shape(3200, 3, 400)     # TH odd
+
+
+@pytest.mark.parametrize("shape,threads", [((100, 400), 1024),
+                                           ((200, 200), 1024),
+                                           ((160, 320), None)])
+def test_persistent_plan_walk_threads(shape, threads):
+    """The persistent plan takes the balanced list walk (1024 threads, at
+    most 3 x 1024 quads per pass) where it lowers the busiest SIMD's load;
+    larger tiles keep the column walk's thread count (below 1024 here)."""
+    L, S = 3200, 5
+    escg.set_tile_shape(L, *shape)
+    try:
+        plan = escg.tile_plan(L, S, True)
+    finally:
+        escg.set_tile_shape(L, 0, 0)
+    assert plan is not None and plan[:2] == shape
+    if threads is not None:
+        assert plan[2] == threads
+    else:
+        assert plan[2] < 1024 and plan[2] % 64 == 0
