@@ -67,50 +67,31 @@ __host__ __device__ inline bool stop_met(const uint32_t *c, uint32_t S,
     return mode == ESCG_STOP_FIRST_EXTINCTION ? alive < S : alive <= 1u;
 }
 
-// Counts sites of value 0..S among ndw dwords of LDS; adds into cnt[0..S]
-// (LDS, zeroed beforehand).  Bytes that are not sites hold pad_byte(S),
-// which matches no species.  SM == 8: one-hot byte codes (values 0..7); else
-// byte compares against every species.
-template <int SM>
-__device__ __forceinline__ void count_dwords(const uint32_t *lat32,
-                                             uint32_t ndw, uint32_t S,
-                                             uint32_t *cnt)
+// Counts sites of value 0..S (S > 7) among ndw dwords of LDS by byte
+// compares; adds into cnt[0..S] (LDS, zeroed beforehand).  Bytes that are
+// not sites hold pad_byte(S), which matches no species.
+__device__ __forceinline__ void count_dwords_wide(const uint32_t *lat32,
+                                                  uint32_t ndw, uint32_t S,
+                                                  uint32_t *cnt)
 {
+    constexpr int SM = 32;
     uint32_t c[SM];
 #pragma unroll
     for (int s = 0; s < SM; ++s)
         c[s] = 0;
     uint32_t mine = 0;
-    if constexpr (SM == 8) {
-        // ndw is even (rows are padded to a multiple of 8 bytes)
-        const uint2 *lat64 = reinterpret_cast<const uint2 *>(lat32);
-        auto walk = [&](auto ns) {
-            for (uint32_t i = threadIdx.x; i < (ndw >> 1); i += blockDim.x) {
-                const uint2 v = lat64[i];
-                count_pair8<decltype(ns)::value>(v.x, v.y, c);
-            }
-        };
-        if (S < 4)
-            walk(std::integral_constant<int, 4>{});
-        else if (S < 6)
-            walk(std::integral_constant<int, 6>{});
-        else
-            walk(std::integral_constant<int, 8>{});
-    } else {
-        for (uint32_t i = threadIdx.x; i < ndw; i += blockDim.x) {
-            const uint32_t v = lat32[i];
-            ++mine;
+    for (uint32_t i = threadIdx.x; i < ndw; i += blockDim.x) {
+        const uint32_t v = lat32[i];
+        ++mine;
 #pragma unroll
-            for (int s = 0; s < SM; ++s)
-                if ((uint32_t)s <= S)
-                    c[s] += bytes_ne(v, (uint32_t)s);
-        }
+        for (int s = 0; s < SM; ++s)
+            if ((uint32_t)s <= S)
+                c[s] += bytes_ne(v, (uint32_t)s);
     }
 #pragma unroll
     for (int s = 0; s < SM; ++s) {
         if ((uint32_t)s <= S) {
-            const uint32_t tot =
-                wave_sum(SM == 8 ? c[s] : 4u * mine - c[s]);
+            const uint32_t tot = wave_sum(4u * mine - c[s]);
             if ((threadIdx.x & 63u) == 0 && tot)
                 atomicAdd(&cnt[s], tot);
         }
@@ -296,7 +277,7 @@ __device__ void run_job_lds(const JobDev &J, uint8_t *base, uint8_t *smem,
         if (J.counts && tid <= S)
             J.counts[tid] = pick8(c, tid);
     } else {
-        count_dwords<32>(lat32, ndw, S, s_cnt);
+        count_dwords_wide(lat32, ndw, S, s_cnt);
         __syncthreads();
         stop = stop_met(s_cnt, S, J.mode);
         if (J.counts && tid <= S)
@@ -327,7 +308,7 @@ __device__ void run_job_lds(const JobDev &J, uint8_t *base, uint8_t *smem,
             if (J.counts && tid <= S)
                 J.counts[(size_t)t * (S + 1) + tid] = pick8(c, tid);
         } else {
-            count_dwords<32>(lat32, ndw, S, s_cnt + nxt * 32);
+            count_dwords_wide(lat32, ndw, S, s_cnt + nxt * 32);
             __syncthreads();
             cur = nxt;
             stop = stop_met(s_cnt + cur * 32, S, J.mode);

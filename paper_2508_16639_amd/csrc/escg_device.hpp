@@ -237,41 +237,16 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
     return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
-// Species counting for values 0..7: v_perm with the byte table
-// {1, 2, 4, ..., 128} maps every byte of a dword to its one-hot code (bytes
-// 12, used as padding, map to 0), so the count of species s in the dword is
-// popcount(code & (0x01010101 << s)).
+// Species counting for values 0..7 (densities_kernel): v_perm with the byte
+// table {1, 2, 4, ..., 128} maps every byte of a dword to its one-hot code
+// (bytes 12, used as padding, map to 0), so the count of species s in the
+// dword is popcount(code & (0x01010101 << s)).
 constexpr uint32_t kOneHotLo = 0x08040201u; // table bytes 0..3
 constexpr uint32_t kOneHotHi = 0x80402010u; // table bytes 4..7
 
 __device__ __forceinline__ uint32_t one_hot_bytes(uint32_t v)
 {
     return __builtin_amdgcn_perm(kOneHotHi, kOneHotLo, v);
-}
-
-// Adds the species counts of eight sites (two dwords, values 0..NS-1 or the
-// padding byte 12) to c[0..NS-1]; counts of absent species stay zero, so
-// every species below NS is accumulated without tests.  The one-hot codes
-// of the two dwords are merged nibble-wise: `lo` holds the codes of species
-// 0..3, low nibbles from v1 and high nibbles from v2, `hi` those of species
-// 4..7; one popcount then counts a species in both dwords at once.
-template <int NS>
-__device__ __forceinline__ void count_pair8(uint32_t v1, uint32_t v2,
-                                            uint32_t (&c)[8])
-{
-    static_assert(NS >= 1 && NS <= 8, "one-hot codes cover values 0..7");
-    const uint32_t h1 = one_hot_bytes(v1), h2 = one_hot_bytes(v2);
-    const uint32_t m = 0x0F0F0F0Fu;
-    const uint32_t lo = (h1 & m) | ((h2 << 4) & ~m);
-#pragma unroll
-    for (int s = 0; s < (NS < 4 ? NS : 4); ++s)
-        c[s] += __popc(lo & (0x11111111u << s));
-    if constexpr (NS > 4) {
-        const uint32_t hi = ((h1 >> 4) & m) | (h2 & ~m);
-#pragma unroll
-        for (int s = 4; s < NS; ++s)
-            c[s] += __popc(hi & (0x11111111u << (s - 4)));
-    }
 }
 
 } // namespace escg

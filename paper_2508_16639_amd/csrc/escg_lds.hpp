@@ -20,12 +20,14 @@ struct LdsTables {
     uint32_t ab[2 * SP * SP];     // selection thresholds A, B per (x, y)
                                   // (jobs with dominance probabilities)
     uint32_t dom[32];             // dominance masks
-    uint32_t cnt[64];             // two count rows
+    uint32_t cnt[64];             // count slots (S <= 7: 8 per linear
+                                  // sum) or two count rows (S > 7)
     uint32_t misc[4];
 };
 
-// Row padding must match no species: for S <= 7 (one-hot counting) it is
-// 12, which v_perm maps to a zero byte; above that 0x40, past every species.
+// Row padding must match no species: for S <= 7 it is 12, which the v_perm
+// code tables of the counts map to a zero byte (the value sum takes off 12
+// per padding byte); above that 0x40, past every species.
 __host__ __device__ inline uint8_t pad_byte(uint32_t S)
 {
     return S <= 7 ? (uint8_t)12 : (uint8_t)0x40;

@@ -21,8 +21,6 @@
 
 #include "escg_quad.hpp"
 
-#include <type_traits>
-
 namespace escg {
 
 struct TileGeom {
