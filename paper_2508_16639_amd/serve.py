@@ -246,6 +246,11 @@ class DeviceExecutor:
         # for all of them; any others run alone on the remaining streams
         tiled = [w for w in large if w[1].L % 8 == 0 and w[1].L >= 16]
         alone = [w for w in large if not (w[1].L % 8 == 0 and w[1].L >= 16)]
+        if len(tiled) == 1 and not small and not alone:
+            # a lone large job has the GPU to itself: the persistent kernel
+            # (all of this iteration's MCS in one cooperative launch) is
+            # about twice as fast per MCS as one launch per MCS
+            alone, tiled = tiled, []
         if tiled:
             with torch.cuda.stream(self.streams[0]):
                 escg.step_batch([h["p"] for h, _, _, _ in tiled],
@@ -256,9 +261,10 @@ class DeviceExecutor:
                 ev.record()
                 done.append(ev)
         others = self.streams[1:] or self.streams
-        # one launch per MCS for these too: a cooperative persistent launch
-        # would wait for CUs that the batched launches hold
-        with escg.routing(persistent_min=1 << 30):
+        # one launch per MCS for these too while other launches run: a
+        # cooperative persistent launch would wait for CUs that they hold
+        lone = len(alone) == 1 and not small and not tiled
+        with escg.routing(persistent_min=None if lone else 1 << 30):
             for i, (h, r, m0, n) in enumerate(alone):
                 s = others[i % len(others)]
                 with torch.cuda.stream(s):
