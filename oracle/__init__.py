@@ -21,8 +21,13 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "escg_oracle.c")
-_OUT_DIR = os.path.join(_HERE, "_build")
+# ESCG_ORACLE_SRC names another copy of the C source to build and load
+# instead (the mutation tests plant mistakes in such a copy, never here).
+_SRC = os.environ.get("ESCG_ORACLE_SRC") or os.path.join(_HERE,
+                                                         "escg_oracle.c")
+_OUT_DIR = (os.path.join(os.path.dirname(os.path.abspath(_SRC)), "_build")
+            if os.environ.get("ESCG_ORACLE_SRC") else
+            os.path.join(_HERE, "_build"))
 _LIB_PATH = os.path.join(_OUT_DIR, "liboracle.so")
 
 FIRST_EXTINCTION = 0

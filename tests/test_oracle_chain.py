@@ -155,9 +155,12 @@ def test_L2_block_schedule_mcs_equals_four_rsu_steps(rates, mutual):
     assert g_test(sample(run, n), dist, n) > 1e-4
 
 
-def test_L3_rsu_matches_exact_chain():
+@pytest.mark.parametrize("mutual", [False, True])
+def test_L3_rsu_matches_exact_chain(mutual):
+    # with the mutual pair (2 over 1 in column 1) the orientation of a
+    # vertical pair matters, so "up" and "down" are told apart
     L, S = 3, 3
-    D = O.circulant_matrix(S, [1])
+    D = D_MUTUAL if mutual else O.circulant_matrix(S, [1])
     rates = (1.0, 1.0, 2.0)
     g0 = np.array([1, 2, 3, 0, 1, 2, 3, 0, 2], np.uint8)
     steps = 3
@@ -294,10 +297,11 @@ def test_L2_moore_block_schedule_mcs_equals_four_rsu_steps(rates, mutual):
     assert g_test(sample(run, n), dist, n) > 1e-4
 
 
-def test_L3_moore_rsu_matches_exact_chain():
+@pytest.mark.parametrize("mutual", [False, True])
+def test_L3_moore_rsu_matches_exact_chain(mutual):
     # eight distinct neighbours on L = 3
     L, S = 3, 3
-    D = O.circulant_matrix(S, [1])
+    D = D_MUTUAL if mutual else O.circulant_matrix(S, [1])
     rates = (1.0, 1.0, 2.0)
     g0 = np.array([1, 2, 3, 0, 1, 2, 3, 0, 2], np.uint8)
     dist = {tuple(g0.tolist()): 1.0}
