@@ -428,6 +428,29 @@ def test_resume_split_equals_straight(route):
     assert np.array_equal(ca, np.vstack([cb1, cb2[1:]]))
 
 
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("L,path", [(46340, "tiled"), (46336, "tiled")])
+def test_maximum_lattice_one_mcs_bit_exact(L, path):
+    """The largest lattices the ABI accepts (L*L just under 2^31 sites, the
+    header's ESCG_MAX_L = 46340): one MCS with counts against the oracle,
+    byte for byte.  46340 is not a multiple of 8 (general tile kernel);
+    46336 is, but no persistent plan fits it, so it runs the per-MCS tiled
+    step kernel.  The oracle takes about a minute per case."""
+    S, K = 3, [1]
+    assert L * L < 2 ** 31
+    p, j = pair(L, S, K, 2.0, seed=13)
+    g0 = random_lattice(L, S, seed=21)
+    print(f"[max-L] L={L} stepping on the GPU", flush=True)
+    out, c = gpu_step(p, g0, 7, 1, route=path)
+    print(f"[max-L] L={L} oracle", flush=True)
+    g = g0.copy()
+    del g0
+    rc = O.o2_run(j, g, 7, 1)
+    assert np.array_equal(out, g)
+    assert np.array_equal(c, rc)
+    assert (c.sum(1, dtype=np.uint64) == L * L).all()
+
+
 def test_exchange_only_is_a_permutation_large():
     L, S = 1024, 5
     p, _ = pair(L, S, [1, 3], 1.0, 0.0, 0.0)
