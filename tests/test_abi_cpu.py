@@ -134,6 +134,9 @@ def test_batch_rejects_overlap_and_bad_jobs():
                               C.c_void_p(8192), None) == escg.EINVAL
     assert lib.escg_batch_run(0, None, None, None, None, None, 0, 1, None,
                               None) == escg.OK
+    # an empty step batch is a no-op too (nothing touches the device)
+    assert lib.escg_step_batch(0, None, None, None, None, None) == escg.OK
+    assert lib.escg_step_batch(1, None, None, None, None, None) == escg.EINVAL
 
 
 @pytest.mark.parametrize("flags", [2, 4, 0x80000000, 3])
