@@ -416,6 +416,38 @@ def test_workload_rpsls_L3200_prefix(route):
     assert np.array_equal(host(cnt).reshape(rc.shape), rc)
 
 
+def test_workload_rpsls_L3200_full_launch():
+    """The benchmark's own launch: init + all 1000 MCS of the L=3200 RPSLS
+    workload with counts in one escg_step_mcs call on the default route
+    (the persistent kernel).  Sampled against the oracle: its init and the
+    count rows of the first 20 MCS, which the launch records on the way.
+    At full length: every count row sums to N, the last row is the count
+    of the returned lattice, and the per-MCS tiled kernel reproduces the
+    lattice and all 1001 count rows byte for byte."""
+    w = RPSLS3200
+    N, n_or = w.L * w.L, 20
+    p, j = pair(w.L, w.S, list(w.K), w.ex, w.sel, w.rep, seed=w.seed)
+    lat = torch.empty(N, dtype=torch.uint8, device="cuda:0")
+    cnt = torch.empty((w.mcs + 1) * (w.S + 1), dtype=torch.int32,
+                      device="cuda:0")
+    escg.init(p, lat)
+    g0 = host(lat).copy()
+    escg.step_mcs(p, lat, 0, w.mcs, cnt)
+    assert escg.last_route() == "persistent", escg.last_error()
+    a, ca = host(lat), host(cnt).reshape(w.mcs + 1, w.S + 1)
+    g = j.init()
+    assert np.array_equal(g0, g)
+    rc = O.o2_run(j, g, 0, n_or)
+    assert np.array_equal(ca[:n_or + 1], rc)
+    assert (ca.sum(1, dtype=np.uint64) == N).all()
+    assert a.max() <= w.S
+    assert np.array_equal(ca[-1], np.bincount(a, minlength=w.S + 1))
+    route_to("tiled")
+    b, cb = gpu_step(p, g0, 0, w.mcs, route="tiled")
+    assert np.array_equal(a, b)
+    assert np.array_equal(ca, cb)
+
+
 @pytest.mark.parametrize("route", ["lds", "tiled", "persistent"])
 def test_resume_split_equals_straight(route):
     route_to(route)
