@@ -200,7 +200,10 @@ uint32_t escg_batch_max_L(uint32_t S);
  *   d_results        uint32[n * 34]: job j's {flag, t_ext, counts[0..S]}
  *                    at d_results + 34 j (unused tail words are zeroed)
  * Every job's output equals escg_run_until_extinction on the same job
- * alone, byte for byte. */
+ * alone, byte for byte.  n == 0 returns ESCG_OK and touches nothing (the
+ * pointers may be NULL); with n > 0 a NULL array, an unknown mode,
+ * misaligned or overlapping lattices or an invalid job give ESCG_EINVAL
+ * with nothing enqueued. */
 #define ESCG_BATCH_RESULT_WORDS 34u
 escg_status escg_batch_run(uint32_t n, const escg_params *h_params,
                            const uint64_t *h_offsets, uint8_t *d_lattices,
@@ -222,6 +225,8 @@ escg_status escg_batch_run(uint32_t n, const escg_params *h_params,
  *                    4-byte aligned, pairwise disjoint, updated in place
  *   h_mcs0[n], h_n_mcs[n]  start MCS and number of MCS per job (0: untouched)
  * No counts are recorded (escg_densities reads a lattice afterwards).
+ * n == 0 returns ESCG_OK and touches nothing; with n > 0 a NULL array gives
+ * ESCG_EINVAL.
  * Scratch: one ping-pong lattice per job, stream-ordered. */
 escg_status escg_step_batch(uint32_t n, const escg_params *h_params,
                             uint8_t *const *h_lattices, const uint32_t *h_mcs0,
