@@ -227,6 +227,26 @@ def test_probabilistic_dominance_step_mcs_bit_exact(case, route):
     assert np.array_equal(c, rc)
 
 
+@pytest.mark.parametrize("S,K", [(5, [1, 3]), (13, [1, 2, 5])])
+@pytest.mark.parametrize("moore,prob", [(True, False), (False, True),
+                                        (True, True)])
+def test_persistent_L3200_variants_bit_exact(S, K, moore, prob):
+    """Moore pairs and dominance probabilities on the persistent kernel at
+    the benchmark's lattice size, with the tile plan and walk it uses there
+    (both count paths: S <= 7 and S > 7)."""
+    route_to("persistent")
+    L, n = 3200, 2
+    D = O.circulant_matrix(S, K)
+    P = probabilities(D, seed=S) if prob else None
+    p, j = pair(L, S, None, 51.2, seed=17, replica=1, D=D, moore=moore, P=P)
+    g0 = random_lattice(L, S, seed=S + 1, domain=5)
+    out, c = gpu_step(p, g0, 3, n, route="persistent")
+    ref = g0.copy()
+    rc = O.o2_run(j, ref, 3, n)
+    assert np.array_equal(out, ref)
+    assert np.array_equal(c, rc)
+
+
 @pytest.mark.parametrize("route", ["lds", "tiled", "persistent"])
 def test_probabilities_equal_to_matrix_reproduce_deterministic_bytes(route):
     route_to(route)
