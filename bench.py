@@ -69,9 +69,7 @@ def recorded_profile(name: str):
     return rec
 
 
-def headline(args, torch, escg, w):
-    p = escg.Params(L=w.L, S=w.S, dom=escg.circulant_dom(w.S, w.K), ex=w.ex,
-                    sel=w.sel, rep=w.rep, seed=w.seed, replica=w.replica)
+def headline(args, torch, escg, w, p):
     N = w.L * w.L
     lat = torch.empty(N, dtype=torch.uint8, device="cuda")
     cnt = torch.empty((w.mcs + 1) * (w.S + 1), dtype=torch.int32,
@@ -283,12 +281,16 @@ def main():
     w = workloads.RPSLS3200
 
     from paper_2508_16639_amd import autotune
-    shape = autotune.apply_cached(torch, escg, w.L, w.S)
-    plan = escg.tile_plan(w.L, w.S, True)
+    p = escg.Params(L=w.L, S=w.S, dom=escg.circulant_dom(w.S, w.K), ex=w.ex,
+                    sel=w.sel, rep=w.rep, seed=w.seed, replica=w.replica)
+    tuned = autotune.apply(torch, p, "persistent")
+    shape = tuned.tile if tuned is not p else None
+    p = tuned
+    plan = escg.tile_plan(p, True)
     log(f"[bench] headline {w.name}: warmup {args.warmup}, steps {args.steps}, "
         f"tile plan {plan} (autotuned: {shape is not None}, "
         f"device {autotune.device_key(torch)})")
-    h = headline(args, torch, escg, w)
+    h = headline(args, torch, escg, w, p)
     log(f"[bench] headline {h['value']:.4e} site-updates/s, "
         f"{h['ms_per_step']:.2f} ms/step, kernel {h['kernel_ms']:.2f} ms")
     achieved = BYTES_PER_SU * h["su_per_launch"] / (h["kernel_ms"] * 1e-3) / 1e9
@@ -298,7 +300,7 @@ def main():
     if prof and prof.get("valu_lane_ops_per_launch"):
         # wave64 VALU instructions x 64 lanes per kernel second (every
         # integer VALU instruction the kernel uses issues at full rate,
-        # v_mad_u64_u32 included: paper_2508_16639_amd/valu_rates.hip)
+        # v_mad_u64_u32 included: tests/microbench/valu_rates.hip)
         a = prof["valu_lane_ops_per_launch"] / (h["kernel_ms"] * 1e-3) / 1e12
         alu = {"bound": "alu", "achieved": a, "peak": VALU_PEAK_TLANEOPS,
                "unit": "T lane-instr/s", "frac": a / VALU_PEAK_TLANEOPS,

@@ -68,6 +68,42 @@ typedef int32_t escg_status;
 #define ESCG_STOP_MONOCULTURE      1u /* at most one species 1..S remains    */
 #define ESCG_STOP_NONE             2u /* run the full MCS budget              */
 
+/* Kernel paths of a single job (escg_launch.route, escg_last_route): the
+ * whole lattice in one workgroup's LDS; one tiled launch per MCS; the
+ * persistent tiled kernel (all MCS in one cooperative launch, every tile
+ * resident in LDS). */
+#define ESCG_ROUTE_LDS        1u
+#define ESCG_ROUTE_TILED      2u
+#define ESCG_ROUTE_PERSISTENT 3u
+
+/* Launch choices of one call (all zero: the library decides).  They select
+ * among kernels that produce the same bytes, so they change speed and
+ * occupancy, never results; they are read per call, so threads driving the
+ * library with different choices do not interfere.
+ *   route     0, or ESCG_ROUTE_LDS / ESCG_ROUTE_TILED / ESCG_ROUTE_PERSISTENT
+ *             to force that path of escg_step_mcs / escg_run_until_extinction
+ *             (ESCG_EUNSUPPORTED, nothing enqueued, if it cannot run this
+ *             job: LDS needs L <= escg_batch_max_L(S), persistent needs
+ *             L % 8 == 0 and a tile plan whose tiles are all resident).
+ *             Automatic: persistent if L % 8 == 0 and L >= 72, else the
+ *             whole lattice in one workgroup's LDS if it fits, else one
+ *             tiled launch per MCS.
+ *   tile_h, tile_w   tile shape of the tiled paths (both 0: the planner's
+ *             cost model); must divide L with tile_w % 8 == 0, tile_h even
+ *             >= 4 (EINVAL otherwise); a shape whose tile does not fit the
+ *             LDS is ESCG_EUNSUPPORTED.
+ *   threads   workgroup size cap of the tiled paths and the batch kernel
+ *             (0: automatic; else a multiple of 64, 64..1024, EINVAL
+ *             otherwise).
+ *   wg_per_cu escg_batch_run only: resident workgroups per compute unit
+ *             (0: as many as fit; else 1..8, capped by what fits). */
+typedef struct escg_launch {
+    uint32_t route;
+    uint32_t tile_h, tile_w;
+    uint32_t threads;
+    uint32_t wg_per_cu;
+} escg_launch;
+
 /* Job parameters.  Rates are named by role; only their ratios matter (the
  * paper normalises them into a roulette).  dom[a] bit b (1 <= a, b <= S) is
  * set iff species a dominates species b (the paper's flat matrix entry
@@ -83,6 +119,7 @@ typedef struct escg_params {
     uint32_t replica;  /* independent stream id under the same seed         */
     uint32_t flags;    /* ESCG_FLAG_*; other bits must be 0                 */
     const double *dom_prob; /* NULL, or S*S dominance probabilities (host)  */
+    escg_launch launch; /* kernel choice for this call; all zero = automatic */
 } escg_params;
 
 /* dom_prob: probabilistic dominance, the interaction variant the paper uses
@@ -232,43 +269,18 @@ escg_status escg_step_batch(uint32_t n, const escg_params *h_params,
                             uint8_t *const *h_lattices, const uint32_t *h_mcs0,
                             const uint32_t *h_n_mcs, void *stream);
 
-/* Single-job routing (escg_step_mcs, escg_run_until_extinction), in order:
- *   1. L % 8 == 0 and L >= persistent_min_L: one persistent cooperative
- *      launch keeps every tile in LDS for all MCS (run-until: chunks of such
- *      launches with an exact stop);
- *   2. L <= min(single_lds_max_L, escg_batch_max_L(S)): the whole lattice in
- *      one workgroup's LDS;
- *   3. otherwise one tiled launch per MCS.
- * Defaults: persistent_min_L = 72, single_lds_max_L = 0xFFFFFFFF (as large
- * as fits).  Every path produces the same bytes; the knobs only trade
- * latency for occupancy.  Process-wide; the setters always return
- * ESCG_OK, the getters return the current values. */
-escg_status escg_set_single_lds_max_L(uint32_t L_max);
-escg_status escg_set_persistent_min_L(uint32_t L_min);
-uint32_t escg_single_lds_max_L(void);
-uint32_t escg_persistent_min_L(void);
-
 /* Which kernel path the calling thread's last escg_step_mcs with n_mcs > 0
- * enqueued: the whole lattice in one workgroup's LDS, one tiled launch per
- * MCS, or the persistent tiled kernel (0 before any such call).  When the
- * persistent path is planned but its cooperative launch is refused, the
- * call falls back to per-MCS launches and escg_last_error() says why. */
-#define ESCG_ROUTE_LDS        1u
-#define ESCG_ROUTE_TILED      2u
-#define ESCG_ROUTE_PERSISTENT 3u
+ * or escg_run_until_extinction enqueued (ESCG_ROUTE_*; 0 before any such
+ * call).  When the persistent path is planned but its cooperative launch is
+ * refused, the call falls back to per-MCS launches and escg_last_error()
+ * says why. */
 uint32_t escg_last_route(void);
 
-/* Tile shape used by the tiled paths for lattice side L (the autotuner's
- * knob): tiles of TH x TW sites, which must divide L with TW % 8 == 0 and TH
- * even >= 4 (and L % 8 == 0); TH = TW = 0 removes the override.  A shape
- * that does not fit the device falls back to the planner's choice.
- * Process-wide.  EINVAL for an invalid shape. */
-escg_status escg_set_tile_shape(uint32_t L, uint32_t TH, uint32_t TW);
-
 /* The tile shape and workgroup size the persistent (persistent != 0) or
- * per-MCS tiled path would use for (L, S) on the current device.
- * EUNSUPPORTED if that path cannot run this L. */
-escg_status escg_tile_plan(uint32_t L, uint32_t S, uint32_t persistent,
+ * per-MCS tiled path would use for job p (its L, S and launch choices) on
+ * the current device.  EUNSUPPORTED if that path cannot run the job, EINVAL
+ * for invalid parameters or NULL outputs. */
+escg_status escg_tile_plan(const escg_params *p, uint32_t persistent,
                            uint32_t *TH, uint32_t *TW, uint32_t *threads);
 
 /* Synchronises the current device and reports errors that asynchronous

@@ -1,18 +1,26 @@
-"""Tile-shape autotuner for the tiled kernels.
+"""Autotuner for the launch choices of the tiled and batched kernels.
 
-For a lattice side L and species count S it times the persistent kernel
-(one cooperative launch, LDS-resident tiles) on candidate tile shapes and
-keeps the fastest.  Results are cached in a JSON file keyed by device name,
-L and whether S <= 7 (the two kernel instantiations), and applied with
-escg.set_tile_shape.  Every shape gives the same bytes, so tuning never
-changes results.
+Every choice it makes (tile shape, workgroup size, resident workgroups per
+compute unit) selects among kernels that give the same bytes, so tuning
+never changes results, only speed.  Results are cached in a JSON file keyed
+by architecture, compute-unit count, kernel, lattice side (or side mix) and
+species class (S <= 7 or S > 7: the two kernel instantiations), and applied
+per call through the job's launch choices (escg.Params.with_launch).
+
+Kernels tuned:
+  persistent  the persistent tiled kernel of one large lattice: tile shape
+              (TH, TW) and workgroup size cap (threads);
+  step        the per-MCS tiled kernel (also used by escg_step_batch): tile
+              shape and workgroup size cap;
+  batch       the LDS-resident batch kernel: workgroup size and resident
+              workgroups per CU, for a mix of lattice sides.
 """
 from __future__ import annotations
 
 import json
 import os
 import time
-from typing import Dict, List, Optional, Tuple
+from typing import Dict, List, Optional, Sequence, Tuple
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)),
                      "autotune_cache.json")
@@ -21,7 +29,8 @@ CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)),
 def candidates(L: int, cus: int, max_tiles_per_cu: int = 3
                ) -> List[Tuple[int, int]]:
     """Tile shapes (TH, TW) dividing L, TW % 8 == 0, TH even >= 4, with
-    between cus/2 and max_tiles_per_cu*cus tiles and at most 512 per side."""
+    between cus/8 and max_tiles_per_cu*cus tiles and at most 512 per
+    side."""
     out = []
     if L % 8:
         return out
@@ -32,21 +41,24 @@ def candidates(L: int, cus: int, max_tiles_per_cu: int = 3
             if L % TH:
                 continue
             T = (L // TH) * (L // TW)
-            if cus // 2 <= T <= max_tiles_per_cu * cus:
+            if max(1, cus // 8) <= T <= max_tiles_per_cu * cus:
                 out.append((TH, TW))
     return out
 
 
 def device_key(torch) -> str:
-    """Architecture and compute-unit count: what the tile shape depends on
+    """Architecture and compute-unit count: what the choices depend on
     (marketing names differ between driver versions)."""
     prop = torch.cuda.get_device_properties(0)
     arch = getattr(prop, "gcnArchName", "") or torch.cuda.get_device_name(0)
     return f"{arch.split(':')[0]}|cus={prop.multi_processor_count}"
 
 
-def _key(torch, L: int, S: int) -> str:
-    return f"{device_key(torch)}|L={L}|S<=7={int(S <= 7)}"
+def key(torch, kernel: str, L, S: int) -> str:
+    """Cache key; L is a side or a tuple of sides (a batch's mix)."""
+    side = ",".join(str(int(x)) for x in L) if isinstance(L, (tuple, list)) \
+        else str(int(L))
+    return f"{device_key(torch)}|{kernel}|L={side}|S<=7={int(S <= 7)}"
 
 
 def load_cache() -> Dict[str, dict]:
@@ -56,65 +68,123 @@ def load_cache() -> Dict[str, dict]:
     return {}
 
 
-def apply_cached(torch, escg, L: int, S: int) -> Optional[Tuple[int, int]]:
-    rec = load_cache().get(_key(torch, L, S))
+def _save(k: str, rec: dict) -> None:
+    cache = load_cache()
+    cache[k] = rec
+    with open(CACHE, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+
+
+def lookup(torch, kernel: str, L, S: int) -> Optional[dict]:
+    return load_cache().get(key(torch, kernel, L, S))
+
+
+def launch_choice(rec: Optional[dict]) -> dict:
+    """escg.Params.with_launch keywords of a cache record ({} if none)."""
     if not rec:
-        return None
-    escg.set_tile_shape(L, rec["TH"], rec["TW"])
-    return rec["TH"], rec["TW"]
+        return {}
+    out = {}
+    if rec.get("TH"):
+        out["tile"] = (rec["TH"], rec["TW"])
+    if rec.get("threads"):
+        out["threads"] = rec["threads"]
+    if rec.get("wg_per_cu"):
+        out["wg_per_cu"] = rec["wg_per_cu"]
+    return out
 
 
-def tune(torch, escg, L: int, S: int, K=None, ex: float = 1.0,
-         n_mcs: int = 40, reps: int = 2, limit: int = 24,
-         save: bool = True) -> dict:
-    """Times up to `limit` candidate shapes (those with the least halo
-    overhead first) and records the fastest."""
+def apply(torch, p, kernel: str = "persistent", L=None):
+    """p with the cached choices of `kernel` for its side (or the side mix
+    L), unchanged if none are cached."""
+    kw = launch_choice(lookup(torch, kernel, p.L if L is None else L, p.S))
+    return p.with_launch(**kw) if kw else p
+
+
+def _time(fn, reps: int) -> float:
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    return best
+
+
+def tune_tiled(torch, escg, L: int, S: int, K=None, ex: float = 1.0,
+               kernel: str = "persistent", n_mcs: int = 40, reps: int = 2,
+               limit: int = 16, threads=(512, 768, 1024),
+               save: bool = True) -> dict:
+    """Times up to `limit` tile shapes (least halo overhead first) times the
+    workgroup size caps `threads` on the persistent ("persistent") or
+    per-MCS ("step") tiled kernel and records the fastest."""
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     cands = candidates(L, cus)
     cands.sort(key=lambda s: ((s[0] + 8) * (s[1] + 16)) / (s[0] * s[1]))
     cands = cands[:limit]
+    if kernel == "step":
+        threads = tuple(t for t in threads if t <= 512) or (512,)
     if K is None:
         K = (1,) if S == 3 else tuple(range(1, (S + 1) // 2 + 1))
-    p = escg.Params(L=L, S=S, dom=escg.circulant_dom(S, K), ex=ex, seed=7)
+    route = "persistent" if kernel == "persistent" else "tiled"
+    base = escg.Params(L=L, S=S, dom=escg.circulant_dom(S, K), ex=ex, seed=7,
+                       route=route)
     lat = torch.empty(L * L, dtype=torch.uint8, device="cuda")
     cnt = torch.empty((n_mcs + 1) * (S + 1), dtype=torch.int32, device="cuda")
-    escg.init(p, lat)
-    old_min = escg.persistent_min_L()
-    escg.set_persistent_min_L(0)
+    escg.init(base, lat)
     results = []
-    try:
-        for TH, TW in cands:
-            escg.set_tile_shape(L, TH, TW)
-            if escg.tile_plan(L, S, True) != None and \
-                    escg.tile_plan(L, S, True)[:2] != (TH, TW):
-                continue  # does not fit the device
-            escg.step_mcs(p, lat, 0, 2, cnt)
-            torch.cuda.synchronize()
-            if escg.last_route() != "persistent":
+    seen = set()
+    for TH, TW in cands:
+        for nt in threads:
+            p = base.with_launch(tile=(TH, TW), threads=nt)
+            plan = escg.tile_plan(p, kernel == "persistent")
+            if plan is None or plan in seen:
+                continue  # does not fit, or the same plan as another cap
+            seen.add(plan)
+            try:
+                dt = _time(lambda: escg.step_mcs(p, lat, 0, n_mcs, cnt), reps)
+            except escg.EscgError:
                 continue
-            best = float("inf")
-            for _ in range(reps):
-                t0 = time.perf_counter()
-                escg.step_mcs(p, lat, 0, n_mcs, cnt)
-                torch.cuda.synchronize()
-                best = min(best, time.perf_counter() - t0)
-            results.append({"TH": TH, "TW": TW,
-                            "us_per_mcs": best / n_mcs * 1e6})
-    finally:
-        escg.set_tile_shape(L, 0, 0)
-        escg.set_persistent_min_L(old_min)
+            results.append({"TH": TH, "TW": TW, "threads": plan[2],
+                            "us_per_mcs": dt / n_mcs * 1e6})
     escg.async_status()
     if not results:
         return {}
     win = min(results, key=lambda r: r["us_per_mcs"])
-    rec = {"TH": win["TH"], "TW": win["TW"],
-           "us_per_mcs": win["us_per_mcs"], "n_mcs": n_mcs,
-           "tried": sorted(results, key=lambda r: r["us_per_mcs"])[:8]}
+    rec = dict(win, n_mcs=n_mcs,
+               tried=sorted(results, key=lambda r: r["us_per_mcs"])[:8])
     if save:
-        cache = load_cache()
-        cache[_key(torch, L, S)] = rec
-        with open(CACHE, "w") as f:
-            json.dump(cache, f, indent=1, sort_keys=True)
+        _save(key(torch, kernel, L, S), rec)
+    return rec
+
+
+def tune_batch(torch, escg, params: Sequence, offsets, max_mcs, mode: int,
+               sides, reps: int = 2, threads=(128, 256, 384, 512),
+               wg_per_cu=(0, 1, 2, 3, 4), save: bool = True) -> dict:
+    """Times escg.batch_run on the given batch (its own parameters, offsets
+    and budgets) for each workgroup size and resident workgroups per CU, and
+    records the fastest under the side mix `sides`."""
+    n = len(params)
+    end = max(int(o) + int(p.L) ** 2 for o, p in zip(offsets, params))
+    buf = torch.empty(end, dtype=torch.uint8, device="cuda")
+    res = torch.empty(n * escg.BATCH_RESULT_WORDS, dtype=torch.int32,
+                      device="cuda")
+    results = []
+    for nt in threads:
+        for w in wg_per_cu:
+            ps = [params[0].with_launch(threads=nt, wg_per_cu=w)] + \
+                list(params[1:])
+            dt = _time(lambda: escg.batch_run(ps, offsets, buf, max_mcs, mode,
+                                              True, res), reps)
+            results.append({"threads": nt, "wg_per_cu": w,
+                            "jobs_per_s": n / dt})
+    win = max(results, key=lambda r: r["jobs_per_s"])
+    rec = dict(win, n_jobs=n,
+               tried=sorted(results, key=lambda r: -r["jobs_per_s"])[:8])
+    if save:
+        _save(key(torch, "batch", tuple(sides), params[0].S), rec)
     return rec
 
 
@@ -122,6 +192,7 @@ if __name__ == "__main__":
     import sys
     import torch
     from paper_2508_16639_amd import escg
-    for arg in sys.argv[1:] or ["3200:5"]:
-        L, S = (int(x) for x in arg.split(":"))
-        print(L, S, json.dumps(tune(torch, escg, L, S)), flush=True)
+    for arg in sys.argv[1:] or ["persistent:3200:5"]:
+        kern, L, S = arg.split(":")
+        print(arg, json.dumps(tune_tiled(torch, escg, int(L), int(S),
+                                         kernel=kern)), flush=True)

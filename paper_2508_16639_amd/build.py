@@ -33,13 +33,9 @@ def hipcc() -> str:
     return exe
 
 
-VALU_RATES_SRC = os.path.join(PKG, "valu_rates.hip")
-VALU_RATES_BIN = os.path.join(PKG, "valu_rates")
-
 
 def build(verbose: bool = False) -> str:
-    """Compiles libescg.so and the valu_rates microbenchmark (always; no
-    staleness shortcut)."""
+    """Compiles libescg.so (always; no staleness shortcut)."""
     tmp = LIB_PATH + f".tmp{os.getpid()}"
     cmd = [hipcc(), *HIPCC_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", *SOURCES,
            "-o", tmp]
@@ -47,14 +43,6 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB_PATH)
-    tmp = VALU_RATES_BIN + f".tmp{os.getpid()}"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           VALU_RATES_SRC, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, VALU_RATES_BIN)
     return LIB_PATH
 
 

@@ -190,12 +190,16 @@ class Run:
         cnt = torch.empty((n + 1) * (self.S + 1), dtype=torch.int32,
                           device="cuda")
         escg.step_mcs(self.p, self.lat, self.done, n, cnt)
+        # a persistent launch that gave up a neighbour wait leaves an
+        # invalid lattice: raise (EscgError) before anything is written
+        escg.async_status()
         rows = cnt.cpu().numpy().view(np.uint32).reshape(n + 1, self.S + 1)
         for k in range(1, n + 1):
             if _monoculture(rows[k]):
                 if k < n:  # re-run exactly k MCS from the chunk's start
                     self.lat.copy_(start)
                     escg.step_mcs(self.p, self.lat, self.done, k, None)
+                    escg.async_status()
                 self.done += k
                 return rows[1:k + 1], True
         self.done += n
@@ -208,6 +212,7 @@ def main(argv: Optional[List[str]] = None) -> int:
     from . import escg
     escg.lib()
     run = Run(args, torch, escg)
+    escg.async_status()  # start from a clean device error record
     out = None
     if args.save or args.resume:
         out = args.resume if (args.resume and not args.save) else args.save

@@ -904,32 +904,81 @@ std::vector<uint32_t> selection_thresholds(const escg_params *p, uint32_t T1,
     return ab;
 }
 
-// Device scratch released stream-ordered when it goes out of scope (after
-// every launch that the scope enqueued).
-struct StreamBuf {
+// The calling thread's last error text and kernel path (escg_last_error,
+// escg_last_route).
+thread_local char g_last_error[160] = "";
+thread_local uint32_t g_last_route = 0;
+
+escg_status last_hip(hipError_t e)
+{
+    if (e == hipSuccess)
+        return ESCG_OK;
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s",
+                  hipGetErrorName(e), hipGetErrorString(e));
+    return ESCG_EDEVICE;
+}
+
+// Scratch of one call: stream-ordered allocations released after the call's
+// last launch (base == null), or carved in order from a fixed device span
+// (base != null: the no-allocation entry point's static array).
+struct Arena {
     hipStream_t st;
-    void *ptr = nullptr;
-    explicit StreamBuf(hipStream_t s) : st(s) {}
-    ~StreamBuf()
+    uint8_t *base = nullptr;
+    size_t cap = 0, used = 0;
+    std::vector<void *> owned;
+    explicit Arena(hipStream_t s, uint8_t *b = nullptr, size_t c = 0)
+        : st(s), base(b), cap(c) {}
+    ~Arena()
     {
-        if (ptr)
-            (void)hipFreeAsync(ptr, st);
+        for (void *q : owned)
+            (void)hipFreeAsync(q, st);
     }
-    StreamBuf(const StreamBuf &) = delete;
-    StreamBuf &operator=(const StreamBuf &) = delete;
+    Arena(const Arena &) = delete;
+    Arena &operator=(const Arena &) = delete;
+    static size_t round(size_t b) { return (b + 255) & ~(size_t)255; }
+    escg_status take(size_t bytes, void **out)
+    {
+        *out = nullptr;
+        if (!base) {
+            if (hipMallocAsync(out, bytes, st) != hipSuccess) {
+                *out = nullptr;
+                return ESCG_ENOMEM;
+            }
+            owned.push_back(*out);
+            return ESCG_OK;
+        }
+        if (used + round(bytes) > cap) {
+            std::snprintf(g_last_error, sizeof(g_last_error),
+                          "needs %zu bytes of static scratch, %zu available",
+                          used + round(bytes), cap);
+            return ESCG_ENOMEM;
+        }
+        *out = base + used;
+        used += round(bytes);
+        return ESCG_OK;
+    }
 };
 
-// Copies host words to new stream-ordered device memory held by `buf`.
-escg_status upload_words(const std::vector<uint32_t> &h, StreamBuf &buf)
+// Copies host words into new scratch of `ar`.
+escg_status upload_words(const std::vector<uint32_t> &h, Arena &ar,
+                         const uint32_t **out)
 {
-    if (hipMallocAsync(&buf.ptr, h.size() * 4, buf.st) != hipSuccess) {
-        buf.ptr = nullptr;
-        return ESCG_ENOMEM;
-    }
-    if (hipMemcpyAsync(buf.ptr, h.data(), h.size() * 4, hipMemcpyHostToDevice,
-                       buf.st) != hipSuccess)
+    void *q = nullptr;
+    escg_status s = ar.take(h.size() * 4, &q);
+    if (s != ESCG_OK)
+        return s;
+    if (hipMemcpyAsync(q, h.data(), h.size() * 4, hipMemcpyHostToDevice,
+                       ar.st) != hipSuccess)
         return ESCG_EDEVICE;
+    *out = static_cast<const uint32_t *>(q);
     return ESCG_OK;
+}
+
+// A tile shape the tiled paths accept for side L.
+bool valid_shape(uint32_t L, uint32_t TH, uint32_t TW)
+{
+    return L % 8 == 0 && TW >= 8 && TW % 8 == 0 && L % TW == 0 && TH >= 4 &&
+           TH % 2 == 0 && L % TH == 0;
 }
 
 escg_status validate(const escg_params *p)
@@ -953,6 +1002,15 @@ escg_status validate(const escg_params *p)
     if (!((p->rate_ex + p->rate_sel) + p->rate_rep > 0.0))
         return ESCG_EINVAL;
     if (p->dom[0] != 0)
+        return ESCG_EINVAL;
+    const escg_launch &ln = p->launch;
+    if (ln.route > ESCG_ROUTE_PERSISTENT || ln.wg_per_cu > 8)
+        return ESCG_EINVAL;
+    if (ln.threads != 0 &&
+        (ln.threads % 64 != 0 || ln.threads < 64 || ln.threads > 1024))
+        return ESCG_EINVAL;
+    if ((ln.tile_h != 0 || ln.tile_w != 0) &&
+        !valid_shape(p->L, ln.tile_h, ln.tile_w))
         return ESCG_EINVAL;
     const uint32_t valid = (p->S >= 31 ? 0xFFFFFFFFu : ((2u << p->S) - 1u)) &
                            ~1u;
@@ -1038,21 +1096,7 @@ uint32_t lds_max_L(uint32_t S)
     return lds_job_bytes(L, S) + reserve <= lds ? L : 0;
 }
 
-// Single jobs run in the LDS-resident kernel up to this L (one workgroup, so
-// larger single lattices go to the tiled multi-workgroup path).
-std::atomic<uint32_t> g_single_lds_max_L{0xFFFFFFFFu};
 
-thread_local char g_last_error[160] = "";
-thread_local uint32_t g_last_route = 0;
-
-escg_status last_hip(hipError_t e)
-{
-    if (e == hipSuccess)
-        return ESCG_OK;
-    std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s",
-                  hipGetErrorName(e), hipGetErrorString(e));
-    return ESCG_EDEVICE;
-}
 
 // Raises the dynamic-LDS limit of a kernel when the runtime supports it; a
 // refusal is not an error by itself (the launch reports real failures), so
@@ -1237,31 +1281,27 @@ uint32_t tiled_threads(const TileGeom &G, uint32_t cap)
     return nt;
 }
 
-std::atomic<uint32_t> g_tiled_min_L{72};
+// Automatic routing sends a single job with L % 8 == 0 to the persistent
+// kernel from this side on.
+constexpr uint32_t kPersistentMinL = 72;
 
-// Tile-shape overrides per lattice side (autotuner results), both tiled
-// paths.  Guarded by g_shape_mu.
-std::mutex g_shape_mu;
-std::map<uint32_t, std::pair<uint32_t, uint32_t>> g_shape_override;
 
-bool shape_override(uint32_t L, uint32_t &TH, uint32_t &TW)
+// Launch choices that shape a plan: a forced tile shape (0, 0: free) and a
+// workgroup size cap (0: 1024 for the persistent kernel, 512 per MCS).
+struct PlanHints {
+    uint32_t TH = 0, TW = 0, threads = 0;
+};
+
+PlanHints plan_hints(const escg_params *p)
 {
-    std::lock_guard<std::mutex> lk(g_shape_mu);
-    auto it = g_shape_override.find(L);
-    if (it == g_shape_override.end())
-        return false;
-    TH = it->second.first;
-    TW = it->second.second;
-    return true;
+    PlanHints h;
+    h.TH = p->launch.tile_h;
+    h.TW = p->launch.tile_w;
+    h.threads = p->launch.threads;
+    return h;
 }
 
-bool valid_shape(uint32_t L, uint32_t TH, uint32_t TW)
-{
-    return L % 8 == 0 && TW >= 8 && TW % 8 == 0 && L % TW == 0 && TH >= 4 &&
-           TH % 2 == 0 && L % TH == 0;
-}
-
-TiledPlan plan_tiled_uncached(uint32_t L, uint32_t S)
+TiledPlan plan_tiled_uncached(uint32_t L, uint32_t S, const PlanHints &h)
 {
     TiledPlan best;
     if (L % 8 != 0 || L < 16)
@@ -1270,8 +1310,11 @@ TiledPlan plan_tiled_uncached(uint32_t L, uint32_t S)
     const int cus = std::max(1, di.cus);
     const size_t lds_max = di.lds_max ? di.lds_max : 65536;
     double best_cost = 1e300;
-    uint32_t oTH = 0, oTW = 0;
-    const bool forced = shape_override(L, oTH, oTW) && valid_shape(L, oTH, oTW);
+    const uint32_t oTH = h.TH, oTW = h.TW;
+    const bool forced = oTH != 0 && valid_shape(L, oTH, oTW);
+    if (oTH != 0 && !forced)
+        return best;
+    const uint32_t cap = h.threads ? h.threads : 1024u;
     for (uint32_t TW = 8; TW <= L; TW += 8) {
         if (L % TW || (forced && TW != oTW))
             continue;
@@ -1283,13 +1326,13 @@ TiledPlan plan_tiled_uncached(uint32_t L, uint32_t S)
             const size_t lds = G.region_bytes();
             if (lds + tiled_static_lds_bytes(S) + 64 > lds_max)
                 continue;
-            uint32_t nt = tiled_threads(G, 1024);
+            uint32_t nt = tiled_threads(G, cap);
             if (nt == 0)
                 continue;
             // the balanced list walk where it lowers the busiest SIMD's load
             bool list = false;
             uint32_t load = walk_simd_load(G, nt, false);
-            for (uint32_t n = 1024; n >= 256; n -= 256) { // ties: more waves
+            for (uint32_t n = cap & ~255u; n >= 256; n -= 256) { // ties: more waves
                 if (!tile_list_fits(G, n) || G.TW / 4 > n)
                     continue;
                 const uint32_t l = walk_simd_load(G, n, true);
@@ -1322,24 +1365,22 @@ TiledPlan plan_tiled_uncached(uint32_t L, uint32_t S)
     return best;
 }
 
-TiledPlan plan_tiled(uint32_t L, uint32_t S)
+using PlanKey = std::tuple<int, uint32_t, bool, uint32_t, uint32_t, uint32_t>;
+
+TiledPlan plan_tiled(uint32_t L, uint32_t S, const PlanHints &h)
 {
     static std::mutex mu;
-    static std::map<std::tuple<int, uint32_t, bool, uint32_t, uint32_t>,
-                    TiledPlan>
-        cache;
+    static std::map<PlanKey, TiledPlan> cache;
     int dev = 0;
     (void)hipGetDevice(&dev);
-    uint32_t oTH = 0, oTW = 0;
-    shape_override(L, oTH, oTW);
-    const auto key = std::make_tuple(dev, L, S <= 7, oTH, oTW);
+    const PlanKey key = std::make_tuple(dev, L, S <= 7, h.TH, h.TW, h.threads);
     {
         std::lock_guard<std::mutex> lk(mu);
         auto it = cache.find(key);
         if (it != cache.end())
             return it->second;
     }
-    const TiledPlan plan = plan_tiled_uncached(L, S <= 7 ? 7u : 31u);
+    const TiledPlan plan = plan_tiled_uncached(L, S <= 7 ? 7u : 31u, h);
     std::lock_guard<std::mutex> lk(mu);
     cache[key] = plan;
     return plan;
@@ -1349,7 +1390,7 @@ TiledPlan plan_tiled(uint32_t L, uint32_t S)
 // TH even >= 4; no residency requirement.  Cost: halo-inflated area over
 // the whole grid plus a per-tile launch charge, assuming the tiles spread
 // evenly over the CUs.
-TiledPlan plan_step_uncached(uint32_t L, uint32_t S)
+TiledPlan plan_step_uncached(uint32_t L, uint32_t S, const PlanHints &h)
 {
     TiledPlan best;
     if (L % 8 != 0 || L < 16)
@@ -1358,8 +1399,11 @@ TiledPlan plan_step_uncached(uint32_t L, uint32_t S)
     const double cus = std::max(1, di.cus);
     const size_t lds_max = di.lds_max ? di.lds_max : 65536;
     double best_cost = 1e300;
-    uint32_t oTH = 0, oTW = 0;
-    const bool forced = shape_override(L, oTH, oTW) && valid_shape(L, oTH, oTW);
+    const uint32_t oTH = h.TH, oTW = h.TW;
+    const bool forced = oTH != 0 && valid_shape(L, oTH, oTW);
+    if (oTH != 0 && !forced)
+        return best;
+    const uint32_t cap = std::min(h.threads ? h.threads : 512u, 512u);
     for (uint32_t TW = 8; TW <= L && TW <= 512; TW += 8) {
         if (L % TW || (forced && TW != oTW))
             continue;
@@ -1370,7 +1414,7 @@ TiledPlan plan_step_uncached(uint32_t L, uint32_t S)
             const size_t lds = G.region_bytes();
             if (lds + tiled_static_lds_bytes(S) + 64 > lds_max)
                 continue;
-            if (tiled_threads(G, 512) == 0)
+            if (tiled_threads(G, cap) == 0)
                 continue;
             const double T = (double)G.TY * G.TX;
             const double area = (double)(TH + 8) * (TW + 16);
@@ -1382,7 +1426,7 @@ TiledPlan plan_step_uncached(uint32_t L, uint32_t S)
                 best_cost = cost;
                 best.ok = true;
                 best.G = G;
-                best.threads = tiled_threads(G, 512);
+                best.threads = tiled_threads(G, cap);
                 best.lds = lds;
             }
         }
@@ -1390,24 +1434,20 @@ TiledPlan plan_step_uncached(uint32_t L, uint32_t S)
     return best;
 }
 
-TiledPlan plan_step(uint32_t L, uint32_t S)
+TiledPlan plan_step(uint32_t L, uint32_t S, const PlanHints &h)
 {
     static std::mutex mu;
-    static std::map<std::tuple<int, uint32_t, bool, uint32_t, uint32_t>,
-                    TiledPlan>
-        cache;
+    static std::map<PlanKey, TiledPlan> cache;
     int dev = 0;
     (void)hipGetDevice(&dev);
-    uint32_t oTH = 0, oTW = 0;
-    shape_override(L, oTH, oTW);
-    const auto key = std::make_tuple(dev, L, S <= 7, oTH, oTW);
+    const PlanKey key = std::make_tuple(dev, L, S <= 7, h.TH, h.TW, h.threads);
     {
         std::lock_guard<std::mutex> lk(mu);
         auto it = cache.find(key);
         if (it != cache.end())
             return it->second;
     }
-    const TiledPlan plan = plan_step_uncached(L, S <= 7 ? 7u : 31u);
+    const TiledPlan plan = plan_step_uncached(L, S <= 7 ? 7u : 31u, h);
     std::lock_guard<std::mutex> lk(mu);
     cache[key] = plan;
     return plan;
@@ -1445,21 +1485,30 @@ void launch_step(const StepArgs &a, const TiledPlan &sp, bool small,
 // Runs n_mcs MCS of a large lattice with the persistent kernel.  Returns
 // ESCG_EUNSUPPORTED (nothing enqueued) if no plan fits or the cooperative
 // launch is refused; the caller then uses the per-MCS tiled kernel.
-escg_status run_tiled_persistent(const escg_params *p, const Derived &d,
-                                 uint8_t *lattice, uint32_t mcs0,
-                                 uint32_t n_mcs, uint32_t *counts,
-                                 hipStream_t st)
+// Bytes of the persistent kernel's exchange area for a plan: two slots per
+// tile plus the abort word (padded).
+size_t exchange_bytes(const TiledPlan &plan)
 {
-    const TiledPlan plan = plan_tiled(p->L, p->S);
+    const size_t T = (size_t)plan.G.TY * plan.G.TX;
+    return (2 * T * plan.G.slot_dwords() + 64) * 4;
+}
+
+// area: exchange_bytes(plan) bytes of scratch for this launch (its tags and
+// abort word are initialised here).  abort_out (device word, or null):
+// receives the launch's abort word (nonzero if a tile gave up waiting for a
+// neighbour, leaving the lattice invalid).
+escg_status run_tiled_persistent(const escg_params *p, const Derived &d,
+                                 const TiledPlan &plan, uint8_t *lattice,
+                                 uint32_t mcs0, uint32_t n_mcs,
+                                 uint32_t *counts, hipStream_t st,
+                                 uint8_t *area, uint32_t *abort_out = nullptr)
+{
     if (!plan.ok)
         return ESCG_EUNSUPPORTED;
     const TileGeom G = plan.G;
     const uint32_t T = G.TY * G.TX;
     const size_t slot_area = (size_t)T * G.slot_dwords(); // dwords
-    const size_t total = (2 * slot_area + 64) * 4;
-    uint8_t *scr = nullptr;
-    if (hipMallocAsync((void **)&scr, total, st) != hipSuccess)
-        return ESCG_ENOMEM;
+    uint8_t *scr = area;
     TiledArgs a;
     std::memset(&a, 0, sizeof(a));
     a.lattice = lattice;
@@ -1498,7 +1547,9 @@ escg_status run_tiled_persistent(const escg_params *p, const Derived &d,
         (void)hipGetLastError();
         s = ESCG_EUNSUPPORTED;
     }
-    (void)hipFreeAsync(scr, st);
+    if (s == ESCG_OK && abort_out)
+        launch_copy(reinterpret_cast<uint8_t *>(abort_out),
+                    reinterpret_cast<const uint8_t *>(a.abort), 4, st);
     return s;
 }
 
@@ -1515,13 +1566,22 @@ escg_status run_until_persistent(const escg_params *p, const Derived &d,
 {
     const uint32_t L = p->L, S = p->S, N = L * L, W = S + 1;
     const uint32_t chunk_max = 1024;
+    const TiledPlan plan = plan_tiled(L, S, plan_hints(p));
+    if (!plan.ok)
+        return ESCG_EUNSUPPORTED;
+    // counts of a chunk, then the launches' abort words, then the saved
+    // lattice, then the exchange area
     const size_t cnt_bytes = (size_t)(chunk_max + 1) * W * 4;
-    const size_t lat_off = (cnt_bytes + 255) & ~(size_t)255;
+    const size_t lat_off = (cnt_bytes + 8 + 255) & ~(size_t)255;
+    const size_t ex_off = (lat_off + N + 255) & ~(size_t)255;
     uint8_t *scr = nullptr;
-    if (hipMallocAsync((void **)&scr, lat_off + N, st) != hipSuccess)
+    if (hipMallocAsync((void **)&scr, ex_off + exchange_bytes(plan), st) !=
+        hipSuccess)
         return ESCG_ENOMEM;
     uint32_t *cnt = reinterpret_cast<uint32_t *>(scr);
+    uint32_t *abort_w = reinterpret_cast<uint32_t *>(scr + cnt_bytes);
     uint8_t *saved = scr + lat_off;
+    uint8_t *area = scr + ex_off;
     std::vector<uint32_t> h((size_t)(chunk_max + 1) * W);
     std::vector<uint32_t> res(S + 3, 0);
     escg_status s = ESCG_OK;
@@ -1535,24 +1595,29 @@ escg_status run_until_persistent(const escg_params *p, const Derived &d,
             hipStreamSynchronize(st) != hipSuccess)
             s = ESCG_EDEVICE;
     };
-    // the sticky abort word of the persistent kernel is read with the
-    // counts; a change from 0 during this call means a chunk was aborted
-    uint32_t aerr = 0, aerr0 = 0;
+    // each launch's own abort word (abort_w[0]: the chunk, abort_w[1]: a
+    // re-run) is read back with the counts; any nonzero word means that
+    // launch gave up a neighbour wait and its lattice is invalid
+    uint32_t aw[2] = {0, 0};
     auto fetch = [&](uint32_t rows) {
         return hipMemcpyAsync(h.data(), cnt, (size_t)rows * W * 4,
                               hipMemcpyDeviceToHost, st) == hipSuccess &&
-               hipMemcpyFromSymbolAsync(&aerr, HIP_SYMBOL(g_async_error),
-                                        sizeof(aerr), 0,
-                                        hipMemcpyDeviceToHost,
-                                        st) == hipSuccess &&
+               hipMemcpyAsync(aw, abort_w, sizeof(aw), hipMemcpyDeviceToHost,
+                              st) == hipSuccess &&
                hipStreamSynchronize(st) == hipSuccess;
+    };
+    auto timed_out = [&](uint32_t from, uint32_t n) {
+        std::snprintf(g_last_error, sizeof(g_last_error),
+                      "persistent kernel aborted (neighbour wait timed out) "
+                      "in MCS %u..%u", from, from + n - 1);
+        return ESCG_ETIMEOUT;
     };
     // the input state
     launch_fill(cnt, W, 0, st);
+    launch_fill(abort_w, 2, 0, st);
     s = launch_densities(lattice, N, S, cnt, st);
     if (s == ESCG_OK && !fetch(1))
         s = ESCG_EDEVICE;
-    aerr0 = aerr;
     if (s == ESCG_OK && (mode != ESCG_STOP_NONE && stop_met(h.data(), S, mode))) {
         finish(1, 0, h.data());
         (void)hipFreeAsync(scr, st);
@@ -1563,18 +1628,16 @@ escg_status run_until_persistent(const escg_params *p, const Derived &d,
     while (s == ESCG_OK && t < max_mcs) {
         const uint32_t n = std::min(chunk, max_mcs - t);
         launch_copy(saved, lattice, N, st);
-        s = run_tiled_persistent(p, d, lattice, mcs0 + t, n, cnt, st);
+        s = run_tiled_persistent(p, d, plan, lattice, mcs0 + t, n, cnt, st,
+                                 area, abort_w);
         if (s != ESCG_OK)
             break; // EUNSUPPORTED on the first chunk: the caller falls back
         if (!fetch(n + 1)) {
             s = ESCG_EDEVICE;
             break;
         }
-        if (aerr && !aerr0) {
-            std::snprintf(g_last_error, sizeof(g_last_error),
-                          "persistent kernel aborted (neighbour wait timed "
-                          "out) in MCS %u..%u", mcs0 + t, mcs0 + t + n - 1);
-            s = ESCG_ETIMEOUT;
+        if (aw[0]) {
+            s = timed_out(mcs0 + t, n);
             break;
         }
         uint32_t hit = 0;
@@ -1586,10 +1649,18 @@ escg_status run_until_persistent(const escg_params *p, const Derived &d,
         if (hit) {
             if (hit < n) {
                 launch_copy(lattice, saved, N, st);
-                s = run_tiled_persistent(p, d, lattice, mcs0 + t, hit,
-                                         nullptr, st);
+                s = run_tiled_persistent(p, d, plan, lattice, mcs0 + t, hit,
+                                         nullptr, st, area, abort_w + 1);
                 if (s != ESCG_OK)
                     break;
+                if (!fetch(0)) {
+                    s = ESCG_EDEVICE;
+                    break;
+                }
+                if (aw[1]) {
+                    s = timed_out(mcs0 + t, hit);
+                    break;
+                }
             }
             finish(1, t + hit, h.data() + (size_t)hit * W);
             break;
@@ -1608,6 +1679,35 @@ escg_status run_until_persistent(const escg_params *p, const Derived &d,
 }
 
 bool aligned4(const void *p) { return ((uintptr_t)p & 3u) == 0; }
+
+// The path of a single job (escg_step_mcs, escg_run_until_extinction) from
+// its launch choice: forced, or automatic (persistent for L % 8 == 0 and
+// L >= kPersistentMinL when a resident plan exists, else the whole lattice
+// in one workgroup's LDS when it fits, else per-MCS tiled launches).
+enum class Route { kLds, kTiled, kPersistent, kUnsupported };
+
+Route choose_route(const escg_params *p)
+{
+    const uint32_t L = p->L, S = p->S;
+    const bool fits_lds = L <= lds_max_L(S);
+    const auto plan_ok = [&] {
+        return (L & 7u) == 0 && plan_tiled(L, S, plan_hints(p)).ok;
+    };
+    switch (p->launch.route) {
+    case ESCG_ROUTE_LDS:
+        return fits_lds ? Route::kLds : Route::kUnsupported;
+    case ESCG_ROUTE_TILED:
+        return Route::kTiled;
+    case ESCG_ROUTE_PERSISTENT:
+        return plan_ok() ? Route::kPersistent : Route::kUnsupported;
+    default:
+        if ((L & 7u) == 0 && L >= kPersistentMinL && plan_ok())
+            return Route::kPersistent;
+        return fits_lds ? Route::kLds : Route::kTiled;
+    }
+}
+
+
 
 } // namespace
 
@@ -1712,27 +1812,47 @@ escg_status escg_densities(const escg_params *p, const uint8_t *d_lattice,
     return launch_densities(d_lattice, p->L * p->L, p->S, d_counts, st);
 }
 
-escg_status escg_step_mcs(const escg_params *p, uint8_t *d_lattice,
-                          uint32_t mcs0, uint32_t n_mcs, uint32_t *d_counts,
-                          void *stream)
+// escg_step_mcs with its scratch from `ar` (stream-ordered or the static
+// array).  With a fixed arena every byte the call will take is checked
+// against it before anything is enqueued.
+escg_status step_mcs(const escg_params *p, uint8_t *d_lattice, uint32_t mcs0,
+                     uint32_t n_mcs, uint32_t *d_counts, Arena &ar)
 {
     escg_status s = validate(p);
     if (s != ESCG_OK)
         return s;
     if (!d_lattice || !aligned4(d_lattice))
         return ESCG_EINVAL;
-    hipStream_t st = S_(stream);
+    hipStream_t st = ar.st;
     Derived d = derive(p);
-    StreamBuf abuf(st);
+    const uint32_t L = p->L, S = p->S, N = L * L;
+    const Route r = choose_route(p);
+    if (r == Route::kUnsupported)
+        return ESCG_EUNSUPPORTED;
+    const bool persistent = r == Route::kPersistent;
+    const TiledPlan plan =
+        persistent ? plan_tiled(L, S, plan_hints(p)) : TiledPlan{};
+    if (ar.base) {
+        const size_t ab = d.prob ? Arena::round(d.ab.size() * 4) : 0;
+        const size_t rest =
+            r == Route::kLds ? 0
+                             : Arena::round(persistent
+                                                ? std::max<size_t>(
+                                                      exchange_bytes(plan), N)
+                                                : N);
+        if (n_mcs > 0 && ab + rest > ar.cap) {
+            std::snprintf(g_last_error, sizeof(g_last_error),
+                          "needs %zu bytes of static scratch, %zu available",
+                          ab + rest, ar.cap);
+            return ESCG_ENOMEM;
+        }
+    }
     if (d.prob) {
-        s = upload_words(d.ab, abuf);
+        s = upload_words(d.ab, ar, &d.d_ab);
         if (s != ESCG_OK)
             return s;
-        d.d_ab = static_cast<const uint32_t *>(abuf.ptr);
     }
-    const uint32_t L = p->L, S = p->S, N = L * L;
-    const bool persistent = (L & 7u) == 0 && L >= g_tiled_min_L.load();
-    if (!persistent && L <= std::min(g_single_lds_max_L.load(), lds_max_L(S))) {
+    if (r == Route::kLds) {
         JobDev J = make_job(p, d, 0, mcs0, n_mcs, ESCG_STOP_NONE, 0, d_counts,
                             nullptr, 0);
         g_last_route = ESCG_ROUTE_LDS;
@@ -1746,27 +1866,26 @@ escg_status escg_step_mcs(const escg_params *p, uint8_t *d_lattice,
     }
     if (n_mcs == 0)
         return ESCG_OK;
+    // one span serves the exchange area or, if the cooperative launch is
+    // refused, the ping-pong lattice of the per-MCS launches
+    void *span = nullptr;
+    s = ar.take(persistent ? std::max<size_t>(exchange_bytes(plan), N) : N,
+                &span);
+    if (s != ESCG_OK)
+        return s;
     if (persistent) {
-        s = run_tiled_persistent(p, d, d_lattice, mcs0, n_mcs, d_counts, st);
+        s = run_tiled_persistent(p, d, plan, d_lattice, mcs0, n_mcs, d_counts,
+                                 st, static_cast<uint8_t *>(span));
         if (s != ESCG_EUNSUPPORTED) {
             g_last_route = ESCG_ROUTE_PERSISTENT;
             return s;
         }
-        s = ESCG_OK;
-        if (L <= std::min(g_single_lds_max_L.load(), lds_max_L(S))) {
-            // counts row 0 is already written; the LDS path rewrites it
-            JobDev J = make_job(p, d, 0, mcs0, n_mcs, ESCG_STOP_NONE, 0,
-                                d_counts, nullptr, 0);
-            g_last_route = ESCG_ROUTE_LDS;
-            return launch_lds_single(J, d.small, d_lattice, st);
-        }
+        s = ESCG_OK; // refused at launch: one tiled launch per MCS instead
     }
     g_last_route = ESCG_ROUTE_TILED;
-    uint8_t *other = nullptr;
-    if (hipMallocAsync((void **)&other, N, st) != hipSuccess)
-        return ESCG_ENOMEM;
+    uint8_t *other = static_cast<uint8_t *>(span);
     uint8_t *cur = d_lattice, *nxt = other;
-    const TiledPlan sp = plan_step(L, S);
+    const TiledPlan sp = plan_step(L, S, plan_hints(p));
     if (sp.ok) {
         StepArgs a = step_args(p, d, sp);
         for (uint32_t k = 0; k < n_mcs; ++k) {
@@ -1792,9 +1911,15 @@ escg_status escg_step_mcs(const escg_params *p, uint8_t *d_lattice,
     }
     if (cur != d_lattice)
         launch_copy(d_lattice, cur, N, st);
-    s = last_hip(hipGetLastError());
-    (void)hipFreeAsync(other, st);
-    return s;
+    return last_hip(hipGetLastError());
+}
+
+escg_status escg_step_mcs(const escg_params *p, uint8_t *d_lattice,
+                          uint32_t mcs0, uint32_t n_mcs, uint32_t *d_counts,
+                          void *stream)
+{
+    Arena ar(S_(stream));
+    return step_mcs(p, d_lattice, mcs0, n_mcs, d_counts, ar);
 }
 
 escg_status escg_run_until_extinction(const escg_params *p, uint8_t *d_lattice,
@@ -1810,24 +1935,26 @@ escg_status escg_run_until_extinction(const escg_params *p, uint8_t *d_lattice,
         return ESCG_EINVAL;
     hipStream_t st = S_(stream);
     Derived d = derive(p);
-    StreamBuf abuf(st);
+    Arena ar(st);
     if (d.prob) {
-        s = upload_words(d.ab, abuf);
+        s = upload_words(d.ab, ar, &d.d_ab);
         if (s != ESCG_OK)
             return s;
-        d.d_ab = static_cast<const uint32_t *>(abuf.ptr);
     }
     const uint32_t L = p->L, S = p->S, N = L * L;
-    if ((L & 7u) == 0 && L >= g_tiled_min_L.load()) {
+    const Route r = choose_route(p);
+    if (r == Route::kUnsupported)
+        return ESCG_EUNSUPPORTED;
+    if (r == Route::kPersistent) {
         s = run_until_persistent(p, d, d_lattice, mcs0, max_mcs, mode,
                                  d_result, st);
         if (s != ESCG_EUNSUPPORTED) {
             g_last_route = ESCG_ROUTE_PERSISTENT;
             return s;
         }
-        s = ESCG_OK;
+        s = ESCG_OK; // refused at launch: one tiled launch per MCS instead
     }
-    if (L <= std::min(g_single_lds_max_L.load(), lds_max_L(S))) {
+    if (r == Route::kLds) {
         JobDev J = make_job(p, d, 0, mcs0, max_mcs, mode, 0, nullptr,
                             d_result, S + 3);
         g_last_route = ESCG_ROUTE_LDS;
@@ -1836,12 +1963,12 @@ escg_status escg_run_until_extinction(const escg_params *p, uint8_t *d_lattice,
     g_last_route = ESCG_ROUTE_TILED;
     // Large lattice: tile MCS launches with a device stop flag, polled by
     // the host every chunk.
-    uint8_t *scratch = nullptr;
+    uint8_t *scr = nullptr;
     const size_t flags_off = ((size_t)N + 255) & ~(size_t)255;
-    if (hipMallocAsync((void **)&scratch, flags_off + 512, st) != hipSuccess)
+    if (hipMallocAsync((void **)&scr, flags_off + 512, st) != hipSuccess)
         return ESCG_ENOMEM;
-    uint8_t *other = scratch;
-    uint32_t *stw = reinterpret_cast<uint32_t *>(scratch + flags_off);
+    uint8_t *other = scr;
+    uint32_t *stw = reinterpret_cast<uint32_t *>(scr + flags_off);
     uint32_t *cnt2 = stw + 4; // two rows of 32 counts
     launch_fill(stw, 4 + 64, 0, st);
     s = launch_densities(d_lattice, N, S, cnt2, st);
@@ -1851,7 +1978,7 @@ escg_status escg_run_until_extinction(const escg_params *p, uint8_t *d_lattice,
                        0u, S, mode, 0u, d_result);
     TileArgs a = tile_args(p, d);
     a.done = stw;
-    const TiledPlan sp = plan_step(L, S);
+    const TiledPlan sp = plan_step(L, S, plan_hints(p));
     StepArgs sa = sp.ok ? step_args(p, d, sp) : StepArgs{};
     sa.done = stw;
     uint8_t *cur = d_lattice, *nxt = other;
@@ -1862,7 +1989,7 @@ escg_status escg_run_until_extinction(const escg_params *p, uint8_t *d_lattice,
         if (hipMemcpyAsync(&done, stw, sizeof(done), hipMemcpyDeviceToHost,
                            st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess) {
-            (void)hipFreeAsync(scratch, st);
+            (void)hipFreeAsync(scr, st);
             return ESCG_EDEVICE;
         }
         if (done)
@@ -1893,7 +2020,7 @@ escg_status escg_run_until_extinction(const escg_params *p, uint8_t *d_lattice,
     if (cur != d_lattice)
         launch_copy(d_lattice, cur, N, st);
     s = last_hip(hipGetLastError());
-    (void)hipFreeAsync(scratch, st);
+    (void)hipFreeAsync(scr, st);
     return s;
 }
 
@@ -1902,51 +2029,26 @@ uint32_t escg_batch_max_L(uint32_t S)
     return (S < 1 || S > ESCG_MAX_SPECIES) ? 0u : lds_max_L(S);
 }
 
-escg_status escg_set_single_lds_max_L(uint32_t L)
-{
-    g_single_lds_max_L = L;
-    return ESCG_OK;
-}
-
 uint32_t escg_last_route(void) { return g_last_route; }
 
-escg_status escg_set_tile_shape(uint32_t L, uint32_t TH, uint32_t TW)
-{
-    if (TH == 0 && TW == 0) {
-        std::lock_guard<std::mutex> lk(g_shape_mu);
-        g_shape_override.erase(L);
-        return ESCG_OK;
-    }
-    if (!valid_shape(L, TH, TW))
-        return ESCG_EINVAL;
-    std::lock_guard<std::mutex> lk(g_shape_mu);
-    g_shape_override[L] = {TH, TW};
-    return ESCG_OK;
-}
-
-escg_status escg_tile_plan(uint32_t L, uint32_t S, uint32_t persistent,
+escg_status escg_tile_plan(const escg_params *p, uint32_t persistent,
                            uint32_t *TH, uint32_t *TW, uint32_t *threads)
 {
-    if (!TH || !TW || !threads || S < 1 || S > ESCG_MAX_SPECIES)
+    escg_status s = validate(p);
+    if (s != ESCG_OK)
+        return s;
+    if (!TH || !TW || !threads)
         return ESCG_EINVAL;
-    const TiledPlan p = persistent ? plan_tiled(L, S) : plan_step(L, S);
-    if (!p.ok)
+    const PlanHints h = plan_hints(p);
+    const TiledPlan tp =
+        persistent ? plan_tiled(p->L, p->S, h) : plan_step(p->L, p->S, h);
+    if (!tp.ok)
         return ESCG_EUNSUPPORTED;
-    *TH = p.G.TH;
-    *TW = p.G.TW;
-    *threads = p.threads;
+    *TH = tp.G.TH;
+    *TW = tp.G.TW;
+    *threads = tp.threads;
     return ESCG_OK;
 }
-
-escg_status escg_set_persistent_min_L(uint32_t L)
-{
-    g_tiled_min_L = L;
-    return ESCG_OK;
-}
-
-uint32_t escg_single_lds_max_L(void) { return g_single_lds_max_L.load(); }
-
-uint32_t escg_persistent_min_L(void) { return g_tiled_min_L.load(); }
 
 escg_status escg_async_status(int reset)
 {
@@ -1982,7 +2084,7 @@ escg_status escg_step_batch(uint32_t n, const escg_params *h_params,
             return s;
         if (!h_lattices[j] || !aligned4(h_lattices[j]))
             return ESCG_EINVAL;
-        plans[j] = plan_step(p->L, p->S);
+        plans[j] = plan_step(p->L, p->S, plan_hints(p));
         if (!plans[j].ok) {
             std::snprintf(g_last_error, sizeof(g_last_error),
                           "job %u: L = %u has no tile plan (needs L %% 8 == 0, "
@@ -2208,8 +2310,13 @@ escg_status escg_batch_run(uint32_t n, const escg_params *h_params,
         return ESCG_EDEVICE;
     }
     launch_fill(d_queue, 1, 0, st);
+    // launch choices of the batch: those of h_params[0] (workgroup size
+    // capped at the kernel's 512, resident workgroups per CU capped at what
+    // fits)
+    const escg_launch &ln = h_params[0].launch;
     const size_t lds = lds_need;
-    const uint32_t nt = lds_threads(Lmax);
+    const uint32_t nt = ln.threads ? std::min(ln.threads, 512u)
+                                   : lds_threads(Lmax);
     const void *fn = ESCG_KERNEL2(lds_batch_kernel, all_small, prob);
     allow_dynamic_lds(fn, lds);
     int per_cu = 0;
@@ -2217,6 +2324,8 @@ escg_status escg_batch_run(uint32_t n, const escg_params *h_params,
             hipSuccess ||
         per_cu < 1)
         per_cu = 1;
+    if (ln.wg_per_cu)
+        per_cu = std::min(per_cu, (int)ln.wg_per_cu);
     const DeviceInfo di = device_info();
     const uint32_t grid =
         std::min<uint32_t>(n, (uint32_t)std::max(1, di.cus) * per_cu);

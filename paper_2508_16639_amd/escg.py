@@ -8,11 +8,11 @@ There is no CPU fallback: if ``libescg.so`` is missing or fails to load,
 """
 from __future__ import annotations
 
-import contextlib
 import ctypes as C
 import os
+import dataclasses
 from dataclasses import dataclass
-from typing import Optional, Sequence
+from typing import Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -22,6 +22,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)),
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ETIMEOUT = 0, -1, -2, -3, -4, -5
 ROUTE_LDS, ROUTE_TILED, ROUTE_PERSISTENT = 1, 2, 3
 ROUTE_NAMES = {0: "none", 1: "lds", 2: "tiled", 3: "persistent"}
+ROUTE_CODES = {"auto": 0, "lds": 1, "tiled": 2, "persistent": 3}
 STOP_FIRST_EXTINCTION, STOP_MONOCULTURE, STOP_NONE = 0, 1, 2
 BATCH_RESULT_WORDS = 34
 FLAG_MOORE = 1           # ESCG_FLAG_MOORE: 8-way neighbourhood
@@ -37,22 +38,25 @@ class EscgError(RuntimeError):
         self.status = status
 
 
+class CLaunch(C.Structure):
+    _fields_ = [("route", C.c_uint32), ("tile_h", C.c_uint32),
+                ("tile_w", C.c_uint32), ("threads", C.c_uint32),
+                ("wg_per_cu", C.c_uint32)]
+
+
 class CParams(C.Structure):
     _fields_ = [("L", C.c_uint32), ("S", C.c_uint32),
                 ("dom", C.c_uint32 * 32),
                 ("rate_ex", C.c_double), ("rate_sel", C.c_double),
                 ("rate_rep", C.c_double), ("seed", C.c_uint64),
                 ("replica", C.c_uint32), ("flags", C.c_uint32),
-                ("dom_prob", C.c_void_p)]
+                ("dom_prob", C.c_void_p), ("launch", CLaunch)]
 
 
 EXPORTS = ("escg_status_str", "escg_last_error", "escg_circulant_dom", "escg_dom_from_matrix",
            "escg_thresholds", "escg_eps_from_mobility", "escg_init", "escg_densities", "escg_step_mcs",
            "escg_run_until_extinction", "escg_batch_max_L", "escg_batch_run",
-           "escg_step_batch",
-           "escg_set_single_lds_max_L", "escg_set_persistent_min_L",
-           "escg_single_lds_max_L", "escg_persistent_min_L",
-           "escg_async_status", "escg_last_route", "escg_set_tile_shape",
+           "escg_step_batch", "escg_async_status", "escg_last_route",
            "escg_tile_plan")
 
 _lib = None
@@ -95,21 +99,13 @@ def lib():
                                  u32p, u32p, u32, u32, vp, vp]
     L.escg_step_batch.argtypes = [u32, P, C.POINTER(C.c_void_p), u32p,
                                   u32p, vp]
-    L.escg_set_single_lds_max_L.argtypes = [u32]
-    L.escg_single_lds_max_L.argtypes = []
-    L.escg_single_lds_max_L.restype = u32
-    L.escg_persistent_min_L.argtypes = []
-    L.escg_persistent_min_L.restype = u32
-    L.escg_set_persistent_min_L.argtypes = [u32]
     L.escg_async_status.argtypes = [C.c_int]
-    L.escg_set_tile_shape.argtypes = [u32, u32, u32]
-    L.escg_tile_plan.argtypes = [u32, u32, u32, u32p, u32p, u32p]
+    L.escg_tile_plan.argtypes = [P, u32, u32p, u32p, u32p]
     L.escg_last_route.argtypes = []
     L.escg_last_route.restype = u32
     for name in EXPORTS:
         if name not in ("escg_status_str", "escg_batch_max_L",
-                        "escg_last_error", "escg_last_route",
-                        "escg_single_lds_max_L", "escg_persistent_min_L"):
+                        "escg_last_error", "escg_last_route"):
             getattr(L, name).restype = C.c_int32
     _lib = L
     return L
@@ -142,6 +138,11 @@ class Params:
     replica: int = 0
     moore: bool = False      # 8-way (Moore) instead of 4-way neighbourhood
     prob: Optional[object] = None  # S x S dominance probabilities or None
+    # launch choices (escg_launch; all default: the library decides)
+    route: str = "auto"      # "auto", "lds", "tiled" or "persistent"
+    tile: Optional[Tuple[int, int]] = None  # (TH, TW) of the tiled paths
+    threads: int = 0         # workgroup size cap, multiple of 64
+    wg_per_cu: int = 0       # batch kernel: resident workgroups per CU
 
     def c(self) -> CParams:
         p = CParams()
@@ -161,7 +162,17 @@ class Params:
             p._keep = P  # the array must outlive the call
         else:
             p.dom_prob = None
+        p.launch.route = ROUTE_CODES[self.route]
+        p.launch.tile_h, p.launch.tile_w = (
+            (int(self.tile[0]), int(self.tile[1])) if self.tile else (0, 0))
+        p.launch.threads = int(self.threads)
+        p.launch.wg_per_cu = int(self.wg_per_cu)
         return p
+
+    def with_launch(self, **kw) -> "Params":
+        """A copy with other launch choices (route, tile, threads,
+        wg_per_cu); the job itself is unchanged."""
+        return dataclasses.replace(self, **kw)
 
 
 def circulant_dom(S: int, K) -> list:
@@ -204,46 +215,12 @@ def batch_max_L(S: int = 3) -> int:
     return int(lib().escg_batch_max_L(int(S)))
 
 
-def persistent_min_L() -> int:
-    return int(lib().escg_persistent_min_L())
-
-
-def single_lds_max_L() -> int:
-    return int(lib().escg_single_lds_max_L())
-
-
-@contextlib.contextmanager
-def routing(single_lds_max: Optional[int] = None,
-            persistent_min: Optional[int] = None):
-    """Sets the single-job routing knobs inside the block and restores the
-    previous values afterwards."""
-    old = (single_lds_max_L(), persistent_min_L())
-    try:
-        if single_lds_max is not None:
-            set_single_lds_max_L(single_lds_max)
-        if persistent_min is not None:
-            set_persistent_min_L(persistent_min)
-        yield
-    finally:
-        set_single_lds_max_L(old[0])
-        set_persistent_min_L(old[1])
-
-
-def set_persistent_min_L(L: int) -> None:
-    _check(lib().escg_set_persistent_min_L(int(L)),
-           "escg_set_persistent_min_L")
-
-
-def set_tile_shape(L: int, TH: int = 0, TW: int = 0) -> None:
-    """Force the tiled paths' tile shape for side L (0, 0 clears)."""
-    _check(lib().escg_set_tile_shape(int(L), int(TH), int(TW)),
-           "escg_set_tile_shape")
-
-
-def tile_plan(L: int, S: int, persistent: bool = True):
-    """(TH, TW, threads) the tiled path would use, or None."""
+def tile_plan(p: Params, persistent: bool = True):
+    """(TH, TW, threads) the persistent (or per-MCS) tiled path would use
+    for job p with its launch choices, or None."""
     a, b, c = C.c_uint32(), C.c_uint32(), C.c_uint32()
-    s = lib().escg_tile_plan(int(L), int(S), 1 if persistent else 0,
+    cp = p.c()
+    s = lib().escg_tile_plan(C.byref(cp), 1 if persistent else 0,
                              C.byref(a), C.byref(b), C.byref(c))
     if s == EUNSUPPORTED:
         return None
@@ -264,11 +241,6 @@ def last_error() -> str:
 def async_status(reset: bool = True) -> None:
     """Raises EscgError if an asynchronous kernel recorded a device error."""
     _check(lib().escg_async_status(1 if reset else 0), "escg_async_status")
-
-
-def set_single_lds_max_L(L: int) -> None:
-    _check(lib().escg_set_single_lds_max_L(int(L)),
-           "escg_set_single_lds_max_L")
 
 
 # ---------------------------------------------------------------------------

@@ -209,6 +209,9 @@ class DeviceExecutor:
                                 replica=0)
 
     def is_small(self, req) -> bool:
+        """Whole lattice fits one workgroup's LDS beside the rule tables of
+        its kernel instantiation (S <= 7 or S > 7; the two run as separate
+        batches, so an S > 7 job never shrinks the S <= 7 limit)."""
         if req.S not in self.small_max:
             self.small_max[req.S] = self.escg.batch_max_L(req.S)
         return req.L <= self.small_max[req.S]
@@ -222,6 +225,15 @@ class DeviceExecutor:
         return {"p": p, "lat": lat}
 
     def advance(self, work):
+        try:
+            self._advance(work)
+        except Exception:
+            # work may already be enqueued on the side streams: let it end
+            # before the caller frees (and the allocator reuses) lattices
+            self.torch.cuda.synchronize()
+            raise
+
+    def _advance(self, work):
         torch, escg = self.torch, self.escg
         small = [(h, r, m0, n) for h, r, m0, n in work if self.is_small(r)]
         large = [(h, r, m0, n) for h, r, m0, n in work if not self.is_small(r)]
@@ -230,24 +242,32 @@ class DeviceExecutor:
         self.batch_stream.wait_stream(cur)
         for s in self.streams:
             s.wait_stream(cur)
-        if small:
-            # one persistent launch for all small jobs; lattices live in
-            # separate tensors, so pass offsets from the lowest address
-            base = min(h["lat"].data_ptr() for h, _, _, _ in small)
-            top = max(h["lat"].data_ptr() + r.L * r.L for h, r, _, _ in small)
+        # small jobs: one persistent batched launch per kernel instantiation
+        # (S <= 7 and S > 7 tables), one after the other on the batch stream
+        res_keep = []
+        for group in ([w for w in small if w[1].S <= 7],
+                      [w for w in small if w[1].S > 7]):
+            if not group:
+                continue
+            # lattices live in separate tensors: offsets from the lowest
+            base = min(h["lat"].data_ptr() for h, _, _, _ in group)
+            top = max(h["lat"].data_ptr() + r.L * r.L for h, r, _, _ in group)
             view = _DevView(base, top - base)
-            offs = [h["lat"].data_ptr() - base for h, _, _, _ in small]
-            res = torch.empty(len(small) * escg.BATCH_RESULT_WORDS,
+            offs = [h["lat"].data_ptr() - base for h, _, _, _ in group]
+            res = torch.empty(len(group) * escg.BATCH_RESULT_WORDS,
                               dtype=torch.int32, device="cuda")
             with torch.cuda.stream(self.batch_stream):
-                escg.batch_run([h["p"] for h, _, _, _ in small], offs, view,
-                               [n for _, _, _, n in small],
+                escg.batch_run([h["p"] for h, _, _, _ in group], offs, view,
+                               [n for _, _, _, n in group],
                                escg.STOP_NONE, False, res,
-                               mcs0=[m0 for _, _, m0, _ in small])
+                               mcs0=[m0 for _, _, m0, _ in group])
+            res_keep.append(res)
+        if small:
+            with torch.cuda.stream(self.batch_stream):
                 ev = torch.cuda.Event()
                 ev.record()
                 done.append(ev)
-            self._res = res  # alive until the iteration completes
+            self._res = res_keep  # alive until the iteration completes
         # large jobs with a tile plan advance together, one launch per MCS
         # for all of them; any others run alone on the remaining streams
         tiled = [w for w in large if w[1].L % 8 == 0 and w[1].L >= 16]
@@ -270,14 +290,14 @@ class DeviceExecutor:
         # one launch per MCS for these too while other launches run: a
         # cooperative persistent launch would wait for CUs that they hold
         lone = len(alone) == 1 and not small and not tiled
-        with escg.routing(persistent_min=None if lone else 1 << 30):
-            for i, (h, r, m0, n) in enumerate(alone):
-                s = others[i % len(others)]
-                with torch.cuda.stream(s):
-                    escg.step_mcs(h["p"], h["lat"], m0, n, None)
-                    ev = torch.cuda.Event()
-                    ev.record()
-                    done.append(ev)
+        for i, (h, r, m0, n) in enumerate(alone):
+            s = others[i % len(others)]
+            p = h["p"] if lone else h["p"].with_launch(route="tiled")
+            with torch.cuda.stream(s):
+                escg.step_mcs(p, h["lat"], m0, n, None)
+                ev = torch.cuda.Event()
+                ev.record()
+                done.append(ev)
         for ev in done:
             cur.wait_event(ev)
         cur.synchronize()

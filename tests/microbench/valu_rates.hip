@@ -8,9 +8,11 @@
 // issues at full rate, 0.67 for a two-instruction step would mean one of
 // them takes two issue slots.
 //
-// Build: hipcc --offload-arch=gfx950 -O3 -Xclang -target-feature -Xclang
-//        -packed-fp32-ops valu_rates.hip -o valu_rates
-// (paper_2508_16639_amd/build.py builds it beside libescg.so.)
+// A measurement helper, not part of the library (nothing builds or loads it
+// automatically).  Build and run from the repository root:
+//   hipcc --offload-arch=gfx950 -O3 -Xclang -target-feature -Xclang
+//     -packed-fp32-ops tests/microbench/valu_rates.hip -o gpurun_out/valu_rates
+//   ./gpurun_out/valu_rates
 #include <hip/hip_runtime.h>
 
 #include <cstdint>

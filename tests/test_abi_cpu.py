@@ -168,13 +168,42 @@ def test_moore_flag_is_bit_zero():
     assert re.search(r"#define ESCG_FLAG_MOORE 1u", src)
 
 
-def test_routing_knobs_and_limits_callable_without_gpu():
-    # defaults: persistent kernel from L = 72 (L % 8 == 0), LDS otherwise
-    assert escg.persistent_min_L() == 72
-    assert escg.single_lds_max_L() == 0xFFFFFFFF
-    with escg.routing(single_lds_max=192, persistent_min=400):
-        assert (escg.single_lds_max_L(), escg.persistent_min_L()) == (192, 400)
-    assert (escg.single_lds_max_L(), escg.persistent_min_L()) == \
-        (0xFFFFFFFF, 72)
+def test_launch_choices_travel_in_params():
+    # per-call launch choices: route, tile shape, thread cap, workgroups per
+    # CU; the library exports no process-wide routing setters
+    p = escg.Params(L=3200, S=5, dom=escg.circulant_dom(5, [1, 3]), ex=51.2)
+    c = p.c()
+    assert (c.launch.route, c.launch.tile_h, c.launch.tile_w,
+            c.launch.threads, c.launch.wg_per_cu) == (0, 0, 0, 0, 0)
+    q = p.with_launch(route="persistent", tile=(100, 400), threads=768,
+                      wg_per_cu=2).c()
+    assert (q.launch.route, q.launch.tile_h, q.launch.tile_w,
+            q.launch.threads, q.launch.wg_per_cu) == (3, 100, 400, 768, 2)
+    assert p.route == "auto"                      # p itself is unchanged
+    L = escg.lib()
+    for name in ("escg_set_single_lds_max_L", "escg_set_persistent_min_L",
+                 "escg_set_tile_shape"):
+        assert not hasattr(L, name), name
+    src = open(os.path.join(ROOT, "include", "escg.h")).read()
+    assert "escg_launch launch;" in src
+
+
+@pytest.mark.parametrize("field,value", [("route", 4), ("threads", 96),
+                                         ("threads", 2048), ("wg_per_cu", 9),
+                                         ("tile_h", 3)])
+def test_invalid_launch_choices_rejected_before_device_work(field, value):
+    p = escg.Params(L=3200, S=5, dom=escg.circulant_dom(5, [1, 3]), ex=51.2)
+    c = p.c()
+    if field == "tile_h":
+        c.launch.tile_h, c.launch.tile_w = value, 400
+    else:
+        setattr(c.launch, field, value)
+    # a bogus device pointer: validation must fail before any use of it
+    s = escg.lib().escg_step_mcs(C.byref(c), C.c_void_p(0x1000), 0, 1, None,
+                                 None)
+    assert s == escg.EINVAL
+
+
+def test_batch_limits_callable_without_gpu():
     assert escg.batch_max_L(0) == 0 and escg.batch_max_L(32) == 0
     assert escg.batch_max_L(3) >= escg.batch_max_L(31) > 0

@@ -1,6 +1,8 @@
 """Parity of the HIP path with the oracle's parallel schedule (O2): lattices,
 per-MCS counts, stop flags and times must be identical, byte for byte.
 All calls go through the C ABI via the ctypes binding."""
+import hashlib
+
 import numpy as np
 import pytest
 
@@ -8,6 +10,8 @@ import oracle as O
 from paper_2508_16639_amd import escg
 from paper_2508_16639_amd.workloads import (RPS64, RPS512, RPSLS3200,
                                             random_lattice)
+from tests import gpu_util
+from tests.golden import make_full_length as golden
 from tests.gpu_util import dev, host, pair, probabilities
 
 pytestmark = pytest.mark.gpu
@@ -15,23 +19,10 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-DEFAULT_ROUTING = (escg.single_lds_max_L(), escg.persistent_min_L())
-
-
 def route_to(route):
-    """Force one of the three MCS paths (all must give the same bytes)."""
-    if route == "lds":
-        escg.set_single_lds_max_L(100000)
-        escg.set_persistent_min_L(100000)
-    elif route == "tiled":
-        escg.set_single_lds_max_L(0)
-        escg.set_persistent_min_L(100000)
-    elif route == "persistent":
-        escg.set_single_lds_max_L(0)
-        escg.set_persistent_min_L(0)
-    else:
-        escg.set_single_lds_max_L(DEFAULT_ROUTING[0])
-        escg.set_persistent_min_L(DEFAULT_ROUTING[1])
+    """Jobs built by pair() from here on ask for one of the three MCS paths
+    (all must give the same bytes), or "auto"."""
+    gpu_util.ROUTE[0] = route
 
 
 @pytest.fixture(autouse=True)
@@ -46,6 +37,8 @@ EXPECT_ROUTE = {"auto": None}
 
 
 def gpu_step(p, g0, mcs0, n, want_counts=True, route=None):
+    if route not in (None, "auto"):
+        p = p.with_launch(route=gpu_util.launch_route(p.L, route))
     lat = dev(g0)
     cnt = (torch.full(((n + 1) * (p.S + 1),), -1, dtype=torch.int32,
                       device="cuda:0") if want_counts else None)
@@ -404,18 +397,32 @@ def test_workload_rps_L64_full():
     assert np.array_equal(host(cnt).reshape(rc.shape), rc)
 
 
-def test_workload_rps_L512_prefix():
-    w = RPS512
-    n = 120
+def _full_length(w, fname):
+    """Init + all MCS of workload w with counts after every MCS in one
+    escg_step_mcs call on the default route, against the oracle's whole run
+    stored in tests/golden/fname (tests/golden/make_full_length.py, oracle
+    only): every count row element by element and the final lattice's
+    SHA-256."""
+    rows, sha, hdr = golden.read(fname)
+    assert hdr["rounds"] == O.Job(2, 1, np.zeros((1, 1), np.uint8), 1.0).rounds
+    assert rows.shape == (w.mcs + 1, w.S + 1)
     p, j = pair(w.L, w.S, list(w.K), w.ex, w.sel, w.rep, seed=w.seed)
     lat = torch.empty(w.L * w.L, dtype=torch.uint8, device="cuda:0")
+    cnt = torch.empty((w.mcs + 1) * (w.S + 1), dtype=torch.int32,
+                      device="cuda:0")
     escg.init(p, lat)
-    cnt = torch.empty((n + 1) * (w.S + 1), dtype=torch.int32, device="cuda:0")
-    escg.step_mcs(p, lat, 0, n, cnt)
-    g = j.init()
-    rc = O.o2_run(j, g, 0, n)
-    assert np.array_equal(host(lat), g)
-    assert np.array_equal(host(cnt).reshape(rc.shape), rc)
+    assert np.array_equal(host(lat), j.init())
+    escg.step_mcs(p, lat, 0, w.mcs, cnt)
+    route = escg.last_route()
+    got = host(cnt).reshape(rows.shape)
+    bad = np.argwhere(got != rows)
+    assert bad.size == 0, f"first differing count row {bad[0][0]} ({route})"
+    assert hashlib.sha256(host(lat).tobytes()).hexdigest() == sha, route
+    return route
+
+
+def test_workload_rps_L512_full_length_vs_oracle():
+    assert _full_length(RPS512, "rps_L512_10000mcs.txt") == "persistent"
 
 
 @pytest.mark.parametrize("route", ["tiled", "persistent"])
@@ -434,6 +441,13 @@ def test_workload_rpsls_L3200_prefix(route):
     rc = O.o2_run(j, g, 0, n)
     assert np.array_equal(host(lat), g)
     assert np.array_equal(host(cnt).reshape(rc.shape), rc)
+
+
+def test_workload_rpsls_L3200_full_length_vs_oracle():
+    """The benchmark's own launch (init + 1000 MCS with counts, persistent
+    kernel, default plan and the autotuned one) against the oracle's full
+    run: all 1001 count rows and the final lattice."""
+    assert _full_length(RPSLS3200, "rpsls_L3200_1000mcs.txt") == "persistent"
 
 
 def test_workload_rpsls_L3200_full_launch():
@@ -537,26 +551,23 @@ def test_tile_shapes_give_identical_bytes(shape):
     L, S = 3200, 5
     p, _ = pair(L, S, [1, 3], 51.2, seed=21)
     g0 = random_lattice(L, S, seed=8, domain=5)
-    route_to("tiled")
     ref, cref = gpu_step(p, g0, 7, 6, route="tiled")
-    route_to("persistent")
-    escg.set_tile_shape(L, *shape)
-    try:
-        plan = escg.tile_plan(L, S, True)
-        got, cgot = gpu_step(p, g0, 7, 6)
-        if plan is not None and plan[:2] == shape:
-            assert escg.last_route() == "persistent"
-    finally:
-        escg.set_tile_shape(L, 0, 0)
+    q = p.with_launch(tile=shape)
+    plan = escg.tile_plan(q, True)
+    assert plan is not None and plan[:2] == shape
+    got, cgot = gpu_step(q, g0, 7, 6, route="persistent")
     assert np.array_equal(got, ref)
     assert np.array_equal(cgot, cref)
 
 
 def test_tile_shape_rejects_invalid():
-    with pytest.raises(escg.EscgError):
-        escg.set_tile_shape(3200, 100, 100)   # TW % 8 != 0
-    with pytest.raises(escg.EscgError):
-        escg.set_tile_shape(3200, 3, 400)     # TH odd
+    p, _ = pair(3200, 5, [1, 3], 51.2)
+    lat = torch.zeros(3200 * 3200, dtype=torch.uint8, device="cuda:0")
+    for bad in [(100, 100), (3, 400)]:          # TW % 8 != 0, TH odd
+        with pytest.raises(escg.EscgError) as e:
+            escg.step_mcs(p.with_launch(tile=bad), lat, 0, 1)
+        assert e.value.status == escg.EINVAL
+    assert int(lat.sum()) == 0                   # nothing was enqueued
 
 
 @pytest.mark.parametrize("shape,threads", [((100, 400), 1024),
@@ -567,13 +578,56 @@ def test_persistent_plan_walk_threads(shape, threads):
     most 3 x 1024 quads per pass) where it lowers the busiest SIMD's load;
     larger tiles keep the column walk's thread count (below 1024 here)."""
     L, S = 3200, 5
-    escg.set_tile_shape(L, *shape)
-    try:
-        plan = escg.tile_plan(L, S, True)
-    finally:
-        escg.set_tile_shape(L, 0, 0)
+    p, _ = pair(L, S, [1, 3], 51.2)
+    plan = escg.tile_plan(p.with_launch(tile=shape), True)
     assert plan is not None and plan[:2] == shape
     if threads is not None:
         assert plan[2] == threads
     else:
         assert plan[2] < 1024 and plan[2] % 64 == 0
+
+
+def test_threads_with_different_routes_do_not_interfere():
+    """Two host threads drive the library at the same time with different
+    launch choices (the persistent kernel and per-MCS tiled launches), each
+    on its own stream: each gets the oracle's bytes and its own route."""
+    import threading
+    L, S, n, reps = 136, 5, 3, 12
+    jobs = {r: pair(L, S, [1, 3], 2.0, seed=31, replica=4, route=r)
+            for r in ("persistent", "tiled")}
+    g0 = random_lattice(L, S, seed=12, domain=3)
+    ref = g0.copy()
+    rc = O.o2_run(jobs["tiled"][1], ref, 0, n * reps)
+    out, errors = {}, []
+
+    def drive(route):
+        try:
+            p = jobs[route][0]
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                lat = dev(g0)
+                cnt = torch.empty((n + 1) * (S + 1), dtype=torch.int32,
+                                  device="cuda:0")
+                rows, seen = [], set()
+                for k in range(reps):
+                    escg.step_mcs(p, lat, k * n, n, cnt)
+                    seen.add(escg.last_route())
+                    rows.append(cnt.clone())
+                s.synchronize()
+            out[route] = (lat.cpu().numpy(), seen,
+                          np.vstack([r.cpu().numpy().view(np.uint32)
+                                     .reshape(n + 1, S + 1)[1:]
+                                     for r in rows]))
+        except Exception as e:  # reported by the main thread
+            errors.append(repr(e))
+
+    ts = [threading.Thread(target=drive, args=(r,)) for r in jobs]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert not errors, errors
+    for route, (lat, seen, rows) in out.items():
+        assert seen == {route}, (route, seen)
+        assert np.array_equal(lat, ref), route
+        assert np.array_equal(rows, rc[1:]), route
