@@ -205,6 +205,26 @@ escg_status escg_step_mcs(const escg_params *p, uint8_t *d_lattice,
                           uint32_t mcs0, uint32_t n_mcs, uint32_t *d_counts,
                           void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as escg_step_mcs, with the same arguments, results (byte for
+ * byte), routing and launch choices, but the call allocates nothing.  Every
+ * scratch buffer it needs (the persistent kernel's exchange area and abort
+ * word, the per-MCS path's ping-pong lattice, the selection thresholds of
+ * dominance probabilities) is carved from one file-scope device array of
+ * ESCG_STATIC_SCRATCH_BYTES bytes per GPU, which the library holds until the
+ * process ends.  A call that would need more returns ESCG_ENOMEM with
+ * nothing enqueued and escg_last_error() giving the bytes needed (the
+ * per-MCS tiled path takes L*L bytes, the persistent path max(exchange
+ * area, L*L), dominance probabilities 8 KiB more: every L <= 8184 fits).  Calls on one GPU share its
+ * array and each call initialises what it uses, so calls whose work
+ * overlaps on the device (different streams, or different host threads)
+ * race on it and give undefined results: serialise them. */
+#define ESCG_STATIC_SCRATCH_BYTES (64u << 20)
+escg_status escg_step_mcs_static(const escg_params *p, uint8_t *d_lattice,
+                                 uint32_t mcs0, uint32_t n_mcs,
+                                 uint32_t *d_counts, void *stream);
+
 /* Runs from absolute MCS mcs0 until the stop condition `mode` holds or
  * max_mcs MCS have been done.  d_result (uint32[S + 3]) receives
  * {flag, t_ext, counts[0..S]}: flag = 1 if the condition held after t_ext

@@ -918,6 +918,35 @@ escg_status last_hip(hipError_t e)
     return ESCG_EDEVICE;
 }
 
+// The no-allocation entry point's scratch: one array per GPU, held until
+// the process ends.  Its name is only a host-side stand-in for the device
+// copy; host code uses the address hipGetSymbolAddress returns for the
+// current device (each GPU has its own copy at its own address).
+static __device__ __align__(256) uint8_t scratch[ESCG_STATIC_SCRATCH_BYTES];
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+escg_status static_scratch(uint8_t **out)
+{
+    static std::mutex mu;
+    static std::vector<uint8_t *> addr;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return last_hip(hipGetLastError());
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)addr.size() <= dev)
+        addr.resize(dev + 1, nullptr);
+    if (!addr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return last_hip(e != hipSuccess ? e : hipErrorInvalidSymbol);
+        addr[dev] = static_cast<uint8_t *>(ptr);
+    }
+    *out = addr[dev];
+    return ESCG_OK;
+}
+
 // Scratch of one call: stream-ordered allocations released after the call's
 // last launch (base == null), or carved in order from a fixed device span
 // (base != null: the no-allocation entry point's static array).
@@ -1919,6 +1948,18 @@ escg_status escg_step_mcs(const escg_params *p, uint8_t *d_lattice,
                           void *stream)
 {
     Arena ar(S_(stream));
+    return step_mcs(p, d_lattice, mcs0, n_mcs, d_counts, ar);
+}
+
+escg_status escg_step_mcs_static(const escg_params *p, uint8_t *d_lattice,
+                                 uint32_t mcs0, uint32_t n_mcs,
+                                 uint32_t *d_counts, void *stream)
+{
+    uint8_t *base = nullptr;
+    escg_status s = static_scratch(&base);
+    if (s != ESCG_OK)
+        return s;
+    Arena ar(S_(stream), base, ESCG_STATIC_SCRATCH_BYTES);
     return step_mcs(p, d_lattice, mcs0, n_mcs, d_counts, ar);
 }
 

@@ -53,11 +53,12 @@ class CParams(C.Structure):
                 ("dom_prob", C.c_void_p), ("launch", CLaunch)]
 
 
+STATIC_SCRATCH_BYTES = 64 << 20   # ESCG_STATIC_SCRATCH_BYTES
 EXPORTS = ("escg_status_str", "escg_last_error", "escg_circulant_dom", "escg_dom_from_matrix",
            "escg_thresholds", "escg_eps_from_mobility", "escg_init", "escg_densities", "escg_step_mcs",
            "escg_run_until_extinction", "escg_batch_max_L", "escg_batch_run",
            "escg_step_batch", "escg_async_status", "escg_last_route",
-           "escg_tile_plan")
+           "escg_tile_plan", "escg_step_mcs_static")
 
 _lib = None
 
@@ -92,6 +93,7 @@ def lib():
     L.escg_init.argtypes = [P, vp, vp]
     L.escg_densities.argtypes = [P, vp, vp, vp]
     L.escg_step_mcs.argtypes = [P, vp, u32, u32, vp, vp]
+    L.escg_step_mcs_static.argtypes = [P, vp, u32, u32, vp, vp]
     L.escg_run_until_extinction.argtypes = [P, vp, u32, u32, u32, vp, vp]
     L.escg_batch_max_L.argtypes = [u32]
     L.escg_batch_max_L.restype = u32
@@ -291,6 +293,19 @@ def step_mcs(p: Params, lattice, mcs0: int, n_mcs: int, counts=None,
                                _ptr(lattice, "torch.uint8", p.L * p.L),
                                int(mcs0), int(n_mcs), cptr, _stream(stream)),
            "escg_step_mcs")
+
+
+def step_mcs_static(p: Params, lattice, mcs0: int, n_mcs: int, counts=None,
+                    stream=None) -> None:
+    """step_mcs without any device allocation (escg_step_mcs_static): scratch
+    comes from the library's fixed per-GPU array; calls whose work overlaps
+    on one GPU must not be issued."""
+    cp = p.c()
+    cptr = (_ptr(counts, "torch.int32", (n_mcs + 1) * (p.S + 1))
+            if counts is not None else None)
+    _check(lib().escg_step_mcs_static(
+        C.byref(cp), _ptr(lattice, "torch.uint8", p.L * p.L), int(mcs0),
+        int(n_mcs), cptr, _stream(stream)), "escg_step_mcs_static")
 
 
 def run_until_extinction(p: Params, lattice, mcs0: int, max_mcs: int,
