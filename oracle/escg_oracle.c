@@ -21,8 +21,10 @@
  *
  *   O2  the parallel-schedule reference: the same pair rule applied on a
  *       conflict-free 2x2-block (Margolus) schedule driven by the
- *       counter-based Philox4x32 generator.  It defines the GPU path's result
- *       exactly.  The paper has no such schedule (it uses racy atomics, Sec.
+ *       counter-based Philox4x32 generator with 7 rounds (the fewest with
+ *       which Salmon et al. report it passing TestU01's BigCrush; the paper
+ *       itself uses Mersenne Twister and cuRAND, so the generator is this
+ *       schedule's own choice).  It defines the GPU path's result exactly.  The paper has no such schedule (it uses racy atomics, Sec.
  *       "ESCG Performance Bottlenecks"); the schedule's definition is stated
  *       in full at o2_pass() below.  Pinned by the L=2 reduction to one RSU
  *       step, an exact one-pass distribution at L=4, invariants, and
@@ -66,7 +68,8 @@ void orc_philox4x32(const uint32_t ctr[4], const uint32_t key[2], int rounds,
     out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
 }
 
-/* One 32-bit word of Philox4x32-10 under the job key (seed). */
+/* One 32-bit word of Philox4x32-R (R = rounds; the schedule uses 7) under */
+/* the job key (seed). */
 static uint32_t draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
                      uint32_t c3, int word, int rounds)
 {

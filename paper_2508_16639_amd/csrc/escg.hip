@@ -220,7 +220,7 @@ __device__ void run_job_lds(const JobDev &J, uint8_t *base, uint8_t *smem,
     if (J.init) {
         const uint32_t nw = (L * L) >> 2;
         for (uint32_t i = tid; i < nw; i += nt) {
-            const Words w = philox10(i, 0u, kTagInit << 8, J.replica, k0, k1);
+            const Words w = philox(i, 0u, kTagInit << 8, J.replica, k0, k1);
 #pragma unroll
             for (uint32_t j = 0; j < 4; ++j) {
                 const uint32_t n = 4u * i + j, r = n / L, c = n - r * L;
@@ -448,7 +448,8 @@ __global__ __launch_bounds__(kTileThreads) void tile_mcs_kernel(TileArgs a)
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     DomPacked dp{a.dom_packed};
     DomTable dt{s_dom};
-    const Words off = philox10(0u, a.t, kTagOffset << 8, a.replica, k0, k1);
+    const Words off =
+        philox_uniform(0u, a.t, kTagOffset << 8, a.replica, k0, k1);
     const int bx_base = (int)(g0 >> 1) - kHaloC / 2; // global bx of m = 0
 #pragma unroll
     for (uint32_t p = 0; p < 4; ++p) {
@@ -470,10 +471,10 @@ __global__ __launch_bounds__(kTileThreads) void tile_mcs_kernel(TileArgs a)
             bxl += bxl < 0 ? (int)Lb : 0;
             bxl -= bxl >= (int)Lb ? (int)Lb : 0;
             const uint32_t qf = (uint32_t)bxf >> 2, ql = (uint32_t)bxl >> 2;
-            const Words rf = philox10(by * Q + qf, a.t, ctr2, a.replica, k0, k1);
+            const Words rf = philox(by * Q + qf, a.t, ctr2, a.replica, k0, k1);
             Words rl = rf;
             if (ql != qf)
-                rl = philox10(by * Q + ql, a.t, ctr2, a.replica, k0, k1);
+                rl = philox(by * Q + ql, a.t, ctr2, a.replica, k0, k1);
 #pragma unroll
             for (uint32_t j = 0; j < 4; ++j) {
                 const uint32_t m = m0 + j;
@@ -771,7 +772,7 @@ __global__ void init_kernel(uint32_t *lat32, uint32_t ndw, uint32_t S,
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ndw;
          i += gridDim.x * blockDim.x) {
-        const Words w = philox10(i, 0u, kTagInit << 8, replica, k0, k1);
+        const Words w = philox(i, 0u, kTagInit << 8, replica, k0, k1);
         uint32_t v = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j)

@@ -3,8 +3,10 @@
 // Schedule and random-number contract (shared by every kernel here; the
 // result of a job is a pure function of it):
 //
-//   key      = (lo32(seed), hi32(seed)); every draw is one Philox4x32-10
-//              block (Salmon et al., SC'11) with counter (c0, c1, c2, c3)
+//   key      = (lo32(seed), hi32(seed)); every draw is one Philox4x32-7
+//              block (Salmon et al., SC'11: seven rounds, the fewest with
+//              which Philox4x32 passes TestU01's BigCrush) with counter
+//              (c0, c1, c2, c3)
 //   init     site n = row*L + col: word (n & 3) of counter
 //              (n >> 2, 0, kTagInit << 8, replica); value = (w * (S+1)) >> 32
 //   offsets  MCS t, pass p: word p of (0, t, kTagOffset << 8, replica);
@@ -30,6 +32,9 @@
 #include <stdint.h>
 
 namespace escg {
+
+// Rounds of every Philox4x32 draw of the schedule.
+constexpr int kPhiloxRounds = 7;
 
 constexpr uint32_t kTagInit = 1u;
 constexpr uint32_t kTagOffset = 2u;
@@ -89,26 +94,51 @@ __device__ __forceinline__ uint32_t xor3_c(uint32_t a, uint32_t b, uint32_t k)
     return a ^ b ^ k;
 }
 
-// Ten Philox rounds for a counter whose word c0 varies across the wave and
-// whose words c1..c3 and key are wave-uniform (all callers here).  The first
-// rounds are written in C so the compiler keeps their uniform parts in
-// scalar registers; from the point where both XOR inputs of a word vary
-// across lanes, the three-way XOR is one v_bitop3 instead of two v_xor.
-__device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1,
-                                          uint32_t c2, uint32_t c3,
-                                          uint32_t k0, uint32_t k1)
+// The kPhiloxRounds rounds for a counter whose word c0 varies across the
+// wave and whose words c1..c3 and key are wave-uniform (all callers here).
+// The first rounds are written in C so the compiler keeps their uniform
+// parts in scalar registers; from the point where both XOR inputs of a word
+// vary across lanes, the three-way XOR is one v_bitop3 instead of two v_xor.
+__device__ __forceinline__ Words philox(uint32_t c0, uint32_t c1, uint32_t c2,
+                                        uint32_t c3, uint32_t k0, uint32_t k1)
 {
+    static_assert(kPhiloxRounds >= 3, "the first three rounds are unrolled");
     ESCG_PHILOX_ROUND(xor3_c, xor3_c);   // c0 varies; c1..c3 uniform
     ESCG_PHILOX_ROUND(xor3_c, xor3_c);   // c2, c3 vary; c0, c1 uniform
     ESCG_PHILOX_ROUND(xor3_vvs, xor3_c); // c0, c1, c2 vary; c3 uniform
 #pragma unroll
-    for (int r = 3; r < 10; ++r)
+    for (int r = 3; r < kPhiloxRounds; ++r)
         ESCG_PHILOX_ROUND(xor3_vvs, xor3_vvs);
     Words o;
     o.w[0] = c0; o.w[1] = c1; o.w[2] = c2; o.w[3] = c3;
     return o;
 }
 #undef ESCG_PHILOX_ROUND
+
+// The same rounds for a counter and key that are uniform across the wave
+// (the per-MCS offset draw): plain C, so the compiler keeps every round on
+// the scalar unit (s_mul_i32 / s_mul_hi_u32) and the vector unit is free.
+__device__ __forceinline__ Words philox_uniform(uint32_t c0, uint32_t c1,
+                                                uint32_t c2, uint32_t c3,
+                                                uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < kPhiloxRounds; ++r) {
+        const uint64_t pa = (uint64_t)kMulA * c0;
+        const uint64_t pb = (uint64_t)kMulB * c2;
+        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)pb;
+        c3 = (uint32_t)pa;
+        c0 = n0;
+        c2 = n2;
+        k0 += kWeylA;
+        k1 += kWeylB;
+    }
+    Words o;
+    o.w[0] = c0; o.w[1] = c1; o.w[2] = c2; o.w[3] = c3;
+    return o;
+}
 
 __device__ __forceinline__ uint32_t pick(const Words &q, uint32_t i)
 {

@@ -85,7 +85,7 @@ __device__ __forceinline__ void lds_pass(uint8_t *lat, uint32_t L,
         return;
     uint32_t c0 = W.c0, pa = W.pa0 + oy * LS;
     for (uint32_t by = W.by0; by < Lb; by += W.rstep) {
-        const Words r = philox10(c0, t, ctr2, replica, k0, k1);
+        const Words r = philox(c0, t, ctr2, replica, k0, k1);
         // the bottom row of the last block row wraps to row 0
         const uint32_t pc = (oy && by == Lb - 1u) ? W.col : pa + LS;
         if (W.full) {
@@ -118,7 +118,8 @@ __device__ __forceinline__ void lds_mcs(uint8_t *lat, uint32_t L, uint32_t LS,
                                         uint32_t k0, uint32_t k1,
                                         const Ctx &qc, const LdsWalk &W)
 {
-    const Words off = philox10(0u, t, kTagOffset << 8, replica, k0, k1);
+    const Words off =
+        philox_uniform(0u, t, kTagOffset << 8, replica, k0, k1);
 #pragma unroll
     for (uint32_t p = 0; p < 4; ++p) {
         lds_pass(lat, L, LS, W, __builtin_amdgcn_readfirstlane(off.w[p]), p,

@@ -159,7 +159,7 @@ __device__ __forceinline__ void tile_pass(uint8_t *lat, const TileGeom &G,
     uint32_t c0 = W.c0, pa = W.pa0 + oy * LS;
     if (ox == 0) {
         for (uint32_t k = W.r0; k < nbr; k += W.rstep) {
-            const Words r = philox10(c0, t, ctr2, replica, k0, k1);
+            const Words r = philox(c0, t, ctr2, replica, k0, k1);
             quad_even(lat, pa, pa + LS, r, qc);
             pa += W.pstep;
             c0 += W.cstep;
@@ -167,7 +167,7 @@ __device__ __forceinline__ void tile_pass(uint8_t *lat, const TileGeom &G,
         }
     } else {
         for (uint32_t k = W.r0; k < nbr; k += W.rstep) {
-            const Words r = philox10(c0, t, ctr2, replica, k0, k1);
+            const Words r = philox(c0, t, ctr2, replica, k0, k1);
             quad_odd(lat, pa, pa + LS, pa + 8, pa + LS + 8, r, qc);
             pa += W.pstep;
             c0 += W.cstep;
@@ -183,7 +183,8 @@ __device__ __forceinline__ void tile_mcs(uint8_t *lat, const TileGeom &G,
                                          uint32_t replica, uint32_t k0,
                                          uint32_t k1, const Ctx &qc)
 {
-    const Words off = philox10(0u, t, kTagOffset << 8, replica, k0, k1);
+    const Words off =
+        philox_uniform(0u, t, kTagOffset << 8, replica, k0, k1);
 #pragma unroll
     for (uint32_t p = 0; p < 4; ++p) {
         tile_pass(lat, G, W, __builtin_amdgcn_readfirstlane(off.w[p]), p, t,
@@ -265,7 +266,7 @@ __device__ __forceinline__ void tile_pass_list(uint8_t *lat,
         if (v[i])
             q[i] = quad_load(lat, T.pa[i] + dy, LS, ox);
         if (i + 1 < kListSlots && v[i + 1]) {
-            r[i + 1] = philox10(T.c0[i + 1], t, ctr2, replica, k0, k1);
+            r[i + 1] = philox(T.c0[i + 1], t, ctr2, replica, k0, k1);
             qs[i + 1] = quad_sel(r[i + 1], qc);
         }
         if (v[i]) {
@@ -275,7 +276,7 @@ __device__ __forceinline__ void tile_pass_list(uint8_t *lat,
         }
     }
     if (p < 3) { // the next pass's first slot, before the barrier
-        rf = philox10(T.c0[0], t, (kTagPass << 8) | (p + 1), replica, k0, k1);
+        rf = philox(T.c0[0], t, (kTagPass << 8) | (p + 1), replica, k0, k1);
         sf = quad_sel(rf, qc);
     }
 }
@@ -286,8 +287,9 @@ __device__ __forceinline__ void tile_mcs_list(uint8_t *lat, const TileGeom &G,
                                               uint32_t replica, uint32_t k0,
                                               uint32_t k1, const Ctx &qc)
 {
-    const Words off = philox10(0u, t, kTagOffset << 8, replica, k0, k1);
-    Words rf = philox10(T.c0[0], t, kTagPass << 8, replica, k0, k1);
+    const Words off =
+        philox_uniform(0u, t, kTagOffset << 8, replica, k0, k1);
+    Words rf = philox(T.c0[0], t, kTagPass << 8, replica, k0, k1);
     QuadSel sf = quad_sel(rf, qc); // slot 0 of pass 0
 #pragma unroll
     for (uint32_t p = 0; p < 4; ++p) {

@@ -53,7 +53,7 @@ int main(int argc, char** argv) {
     const uint32_t nts[] = {256, 512, 64};
     blockDim.x = nts[cases % 3];
     for (uint32_t t = 0; t < n; ++t) {
-      const Words off = philox10(0u, mcs0 + t, kTagOffset << 8, rep, (uint32_t)seed, (uint32_t)(seed >> 32));
+      const Words off = philox(0u, mcs0 + t, kTagOffset << 8, rep, (uint32_t)seed, (uint32_t)(seed >> 32));
       for (uint32_t p = 0; p < 4; ++p)
         for (threadIdx.x = 0; threadIdx.x < blockDim.x; ++threadIdx.x)
           if (prob) lds_pass(lat, L, LS, lds_walk(L, LS), off.w[p], p, mcs0 + t, rep, (uint32_t)seed, (uint32_t)(seed >> 32), qcp);
@@ -61,7 +61,7 @@ int main(int argc, char** argv) {
     }
     blockDim.x = 1; threadIdx.x = 0;
     std::vector<uint8_t> ref = g;
-    orc_o2_run(L, S, D.data(), r[0], r[1], r[2], seed, rep, 10, moore ? 8 : 4, prob ? P.data() : nullptr, mcs0, n, ref.data(), nullptr);
+    orc_o2_run(L, S, D.data(), r[0], r[1], r[2], seed, rep, kPhiloxRounds, moore ? 8 : 4, prob ? P.data() : nullptr, mcs0, n, ref.data(), nullptr);
     bool ok = true;
     for (uint32_t rr = 0; rr < L; ++rr) { for (uint32_t c = 0; c < L; ++c) if (lat[rr*LS+c] != ref[rr*L+c]) ok = false; for (uint32_t c = L; c < LS; ++c) if (lat[rr*LS+c] != pad_byte(S)) ok = false; }
     cases++; if (!ok) { bad++; if (bad < 400) printf("MISMATCH prob=%d moore=%d S=%u L=%u rates=%g,%g,%g\n", (int)prob, (int)moore, S, L, r[0], r[1], r[2]); }

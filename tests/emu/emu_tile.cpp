@@ -14,7 +14,7 @@ extern "C" void orc_circulant_matrix(uint32_t S, uint32_t kmask, uint8_t *D);
 // (threads of one pass touch disjoint blocks, so sequential order is exact).
 static void emu_tile_mcs(uint8_t *lat, const TileGeom &G, uint32_t ty, uint32_t tx, uint32_t t,
                          uint32_t rep, uint32_t k0, uint32_t k1, const QuadCtx &qc, uint32_t bd) {
-  const Words off = philox10(0u, t, kTagOffset << 8, rep, k0, k1);
+  const Words off = philox(0u, t, kTagOffset << 8, rep, k0, k1);
   blockDim.x = bd;
   for (uint32_t p = 0; p < 4; ++p)
     for (threadIdx.x = 0; threadIdx.x < bd; ++threadIdx.x) {
@@ -26,12 +26,12 @@ static void emu_tile_mcs(uint8_t *lat, const TileGeom &G, uint32_t ty, uint32_t 
 // The same with the balanced list walk (tile_pass_list), bd threads.
 static void emu_tile_mcs_list(uint8_t *lat, const TileGeom &G, uint32_t ty, uint32_t tx, uint32_t t,
                               uint32_t rep, uint32_t k0, uint32_t k1, const QuadCtx &qc, uint32_t bd) {
-  const Words off = philox10(0u, t, kTagOffset << 8, rep, k0, k1);
+  const Words off = philox(0u, t, kTagOffset << 8, rep, k0, k1);
   blockDim.x = bd;
   for (uint32_t p = 0; p < 4; ++p)
     for (threadIdx.x = 0; threadIdx.x < bd; ++threadIdx.x) {
       const TileList TL = tile_list(G, ty, tx);
-      Words rf = philox10(TL.c0[0], t, (kTagPass << 8) | p, rep, k0, k1);
+      Words rf = philox(TL.c0[0], t, (kTagPass << 8) | p, rep, k0, k1);
       QuadSel sf = quad_sel(rf, qc);
       tile_pass_list(lat, G, TL, off.w[p], p, t, rep, k0, k1, qc, rf, sf);
     }
@@ -138,7 +138,7 @@ int main() {
     }
     std::vector<uint8_t> ref = g;
     std::vector<uint32_t> rcnt((n + 1) * (S + 1), 0);
-    orc_o2_run(L, S, D.data(), r[0], r[1], r[2], seed, rep, 10, moore ? 8 : 4, nullptr, mcs0, n, ref.data(), rcnt.data());
+    orc_o2_run(L, S, D.data(), r[0], r[1], r[2], seed, rep, kPhiloxRounds, moore ? 8 : 4, nullptr, mcs0, n, ref.data(), rcnt.data());
     for (size_t q = S + 1; q < rcnt.size(); ++q)
       if (rcnt[q] != cnt[q]) { bad++; printf("COUNT MISMATCH L=%u S=%u idx=%zu %u vs %u\n", L, S, q, cnt[q], rcnt[q]); break; }
     if (cur != ref) { bad++; printf("PER-MCS MISMATCH L=%u TH=%u TW=%u S=%u\n", L, c.TH, c.TW, S); }

@@ -62,3 +62,12 @@ def test_philox_words_uniform():
                       for i in range(4096)], dtype=np.uint64).reshape(-1)
     bits = ((words[:, None] >> np.arange(32, dtype=np.uint64)) & 1).mean(0)
     assert np.all(np.abs(bits - 0.5) < 0.02)
+
+
+def test_schedule_round_count_has_published_vectors():
+    # the block schedule draws Philox4x32 with O.SCHEDULE_ROUNDS rounds: the
+    # published known-answer file covers that round count, so the
+    # generator the schedule uses is pinned, not only the 10-round default
+    assert O.SCHEDULE_ROUNDS in {r for r, _, _, _ in _kat_rows()}
+    assert O.Job(2, 1, np.zeros((1, 1), np.uint8), 1.0).rounds == \
+        O.SCHEDULE_ROUNDS

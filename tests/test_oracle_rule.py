@@ -135,5 +135,6 @@ def test_init_map_is_floor_scaling():
     g = O.init_lattice(4, S, seed, rep)
     for n in range(16):
         w = O.philox4x32([n >> 2, 0, 1 << 8, rep],
-                         [seed & 0xFFFFFFFF, seed >> 32])[n & 3]
+                         [seed & 0xFFFFFFFF, seed >> 32],
+                         O.SCHEDULE_ROUNDS)[n & 3]
         assert g[n] == (int(w) * (S + 1)) >> 32
