@@ -14,7 +14,7 @@
  * four passes; each pass tiles the lattice into disjoint 2x2 blocks at a
  * random offset and updates one random internal edge per block, so one MCS
  * is L*L elementary steps, as in the paper's Overall ESCG Loop.  All random
- * numbers come from Philox4x32-10 (Salmon et al., SC'11) keyed by the job
+ * numbers come from Philox4x32-7 (Salmon et al., SC'11) keyed by the job
  * seed, with counters built from (site or block, MCS index, pass, replica):
  * a result depends only on (parameters, input lattice, absolute MCS index),
  * never on launch shape, batching, co-running jobs or how a run is split.
