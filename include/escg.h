@@ -138,9 +138,9 @@ typedef struct escg_params {
 /* flags: the 8-way Moore neighbourhood instead of the 4-way von Neumann one
  * (the paper's --neighbourhood option, Sec. "Single Threaded ESCG in C++").
  * A random-sequential step then picks one of a site's eight neighbours; in
- * the block schedule a block word's bits 0-2 pick one of eight pair slots,
+ * the block schedule a block word's bits 3-5 pick one of eight pair slots,
  * the four axis edges (A,B), (C,D), (A,C), (B,D) once each and the two
- * diagonals (A,D), (B,C) twice each, and bit 3 the orientation, which
+ * diagonals (A,D), (B,C) twice each, and bit 6 the orientation, which
  * updates every one of the 4N Moore pairs at the same rate, 1/16 per
  * pass. */
 #define ESCG_FLAG_MOORE 1u

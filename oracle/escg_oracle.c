@@ -276,18 +276,21 @@ void orc_counts(uint32_t L, uint32_t S, const uint8_t *grid, uint32_t *counts)
 /* Q = ceil((L/2)/4), so one Philox call serves four horizontally adjacent   */
 /* blocks of one block row.  From w:                                         */
 /*   von Neumann neighbourhood (nbhd = 4):                                   */
-/*   bits 0-1  edge:        0 -> (A,B)  1 -> (C,D)  2 -> (A,C)  3 -> (B,D)   */
-/*   bit  2    orientation: 0 -> the first site of the edge is the selected  */
+/*   bits 3-4  edge:        0 -> (A,B)  1 -> (C,D)  2 -> (A,C)  3 -> (B,D)   */
+/*   bit  5    orientation: 0 -> the first site of the edge is the selected  */
 /*                          cell, 1 -> the second one is                     */
 /*   Moore neighbourhood (nbhd = 8):                                         */
-/*   bits 0-2  pair: 0 -> (A,B)  1 -> (C,D)  2 -> (A,C)  3 -> (B,D)          */
+/*   bits 3-5  pair: 0 -> (A,B)  1 -> (C,D)  2 -> (A,C)  3 -> (B,D)          */
 /*                   4 -> (A,D)  5 -> (B,C)  6 -> (A,D)  7 -> (B,C)          */
 /*             (a diagonal lies inside a block for one offset in four, an    */
 /*             axis edge for one in two, so the diagonals take two slots:    */
 /*             every one of the 4N Moore pairs is then updated with the same */
 /*             probability 1/16 per pass, as under random-sequential steps)  */
-/*   bit  3    orientation, as bit 2 above                                   */
+/*   bit  6    orientation, as bit 5 above                                   */
 /*   bits 8-31 u24, the action by the thresholds above                       */
+/*   (bits 0-2 and 6-7, resp. 7, are unused; the pair bits sit at bit 3 so   */
+/*   that a block's pair is the byte offset w & 0x38 (0x78) of an 8-byte     */
+/*   table entry, a choice of this schedule, not of the paper)               */
 /* and the pair rule is applied to (selected cell, neighbour).  Blocks are   */
 /* disjoint, so the order in which blocks are visited is irrelevant.         */
 /* ------------------------------------------------------------------------ */
@@ -318,8 +321,8 @@ static void o2_pass(const o2_job *j, uint32_t t, uint32_t p, uint8_t *grid)
             uint64_t A = (uint64_t)r0 * L + c0, B = (uint64_t)r0 * L + c1;
             uint64_t C = (uint64_t)r1 * L + c0, Dd = (uint64_t)r1 * L + c1;
             uint64_t first, second;
-            uint32_t pair = j->nbhd == 8 ? (w & 7u) : (w & 3u);
-            uint32_t orient = j->nbhd == 8 ? (w >> 3) & 1u : (w >> 2) & 1u;
+            uint32_t pair = j->nbhd == 8 ? (w >> 3) & 7u : (w >> 3) & 3u;
+            uint32_t orient = j->nbhd == 8 ? (w >> 6) & 1u : (w >> 5) & 1u;
             switch (pair) {
             case 0: first = A; second = B; break;
             case 1: first = C; second = Dd; break;

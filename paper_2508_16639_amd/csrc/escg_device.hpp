@@ -15,11 +15,12 @@
 //              (2*by + oy, 2*bx + ox) mod L; block (by, bx) uses word
 //              (bx & 3) of counter (by*Q + (bx >> 2), t, (kTagPass << 8) | p,
 //              replica), Q = ceil((L/2) / 4) quads per block row
-//   word w   edge = w & 3: (A,B), (C,D), (A,C), (B,D) with A top-left,
-//              B top-right, C bottom-left, D bottom-right; bit 2 set: the
-//              second site of the edge is the selected cell; u = w >> 8 is
-//              the 24-bit action draw: exchange if u < T1, selection if
-//              u < T2, else reproduction
+//   word w   edge = (w >> 3) & 3: (A,B), (C,D), (A,C), (B,D) with A
+//              top-left, B top-right, C bottom-left, D bottom-right; bit 5
+//              set: the second site of the edge is the selected cell (Moore:
+//              pair slot (w >> 3) & 7, orientation bit 6); u = w >> 8 is the
+//              24-bit action draw: exchange if u < T1, selection if u < T2,
+//              else reproduction; the remaining low bits are unused
 //
 // The pair rule follows the paper's Algorithm "Elementary Step" (same
 // species: no change; migration swaps; interaction empties the dominated
@@ -197,9 +198,9 @@ __device__ __forceinline__ void pair_rule(uint32_t u, uint32_t T1, uint32_t T2,
 
 // Updates one 2x2 block in LDS.  pA..pD are the LDS byte offsets of the
 // block's top-left, top-right, bottom-left and bottom-right sites.  Von
-// Neumann: bits 0-1 of w pick the edge, bit 2 the orientation; Moore: bits
-// 0-2 pick one of the eight pair slots (edges, then the diagonals (A,D),
-// (B,C) twice each), bit 3 the orientation.  ab (global, or null): the
+// Neumann: bits 3-4 of w pick the edge, bit 5 the orientation; Moore: bits
+// 3-5 pick one of the eight pair slots (edges, then the diagonals (A,D),
+// (B,C) twice each), bit 6 the orientation.  ab (global, or null): the
 // selection thresholds of a job with dominance probabilities, A at
 // [x * Sp + y] and B at [Sp * Sp + x * Sp + y]; a selection draw u then
 // compares v = u - T1 with them (v < A: the selected cell wins, else
@@ -213,8 +214,8 @@ __device__ __forceinline__ void update_block(uint8_t *lat, uint32_t pA,
                                              const uint32_t *ab = nullptr,
                                              uint32_t Sp = 8)
 {
-    const uint32_t e = moore ? (w & 7u) : (w & 3u);
-    const uint32_t o = moore ? (w >> 3) & 1u : (w >> 2) & 1u;
+    const uint32_t e = moore ? (w >> 3) & 7u : (w >> 3) & 3u;
+    const uint32_t o = moore ? (w >> 6) & 1u : (w >> 5) & 1u;
     // value selects (not lvalue ?:, which would select addresses)
     uint32_t f = (e & 1u) ? pC : pA, s = (e & 1u) ? pD : pB;     // 0, 1
     f = (e == 2) ? pA : (e == 3) ? pB : f;                       // 2, 3

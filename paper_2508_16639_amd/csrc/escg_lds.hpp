@@ -14,7 +14,9 @@ namespace escg {
 // S <= 7 (values 0..7), SP = 32 any S <= 31.
 template <int SP>
 struct LdsTables {
-    uint2 sel[256];               // {gather, scatter} selectors
+    uint2 sel[16];                // {gather, scatter} selectors, entry
+                                  // (w & selmask) / 8 of block word w
+    uint32_t selmask;             // 0x38 (von Neumann) or 0x78 (Moore)
     uint16_t rule[6 * SP * SP];   // (x', y') per action (3 used without
                                   // dominance probabilities), x, y
     uint32_t ab[2 * SP * SP];     // selection thresholds A, B per (x, y)
@@ -134,6 +136,7 @@ __device__ inline QuadCtxT<kProb> make_quad_ctx(const LdsTables<SP> &T,
 {
     QuadCtxT<kProb> qc;
     qc.sel = T.sel;
+    qc.selmask = T.selmask;
     qc.rule = reinterpret_cast<const uint8_t *>(T.rule);
     const ActionSplit a = split_actions(T1, T2);
     const uint32_t tb = SP * SP * 2u; // bytes per rule table
@@ -167,6 +170,8 @@ __device__ inline void setup_tables(LdsTables<SP> &T, const uint32_t *dom,
         T.dom[i] = dom[i];
     for (uint32_t i = threadIdx.x; i < 64; i += blockDim.x)
         T.cnt[i] = 0;
+    if (threadIdx.x == 0)
+        T.selmask = moore ? 0x78u : 0x38u;
     if (ab)
         for (uint32_t i = threadIdx.x; i < 2 * SP * SP; i += blockDim.x)
             T.ab[i] = ab[i];

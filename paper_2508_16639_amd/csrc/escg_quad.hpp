@@ -5,13 +5,13 @@
 // The two 8-byte row segments are transposed with v_perm into one dword per
 // block, B = [A, B, C, D] (top-left, top-right, bottom-left, bottom-right).
 // For block word w:
-//   * the low byte of w indexes an LDS table of two v_perm selectors: the
-//     gather selector moves (selected cell, neighbour) = (x, y) into bytes
-//     0 and 1; the scatter selector writes (x', y') back into their places
-//     and keeps the other two sites.  Bits 0-1 (edge) and 2 (orientation)
-//     decide them in the von Neumann neighbourhood, bits 0-2 (pair) and 3
-//     (orientation) in the Moore one; the other bits are unused, so the
-//     table repeats every 8 or 16 entries.
+//   * w & 0x38 (von Neumann: bits 3-4 edge, bit 5 orientation) or w & 0x78
+//     (Moore: bits 3-5 pair, bit 6 orientation) is the byte offset of an
+//     8-byte LDS entry of two v_perm selectors: the gather selector moves
+//     (selected cell, neighbour) = (x, y) into bytes 0 and 1; the scatter
+//     selector writes (x', y') back into their places and keeps the other
+//     two sites.  The 8 (16) entries span 16 (32) dwords, so the 64 lanes'
+//     lookups never meet in a bank except on the same dword (a broadcast).
 //   * the action is picked by comparing w with thresholds pre-shifted into
 //     word space (u = w >> 8 < T  <=>  w <= (T << 8) - 1), which selects
 //     one of three rule tables;
@@ -33,7 +33,8 @@ namespace escg {
 template <bool kProb>
 struct QuadCtxT {
     static constexpr bool kProbabilistic = kProb;
-    const uint2 *sel;     // LDS: 256 {gather, scatter} selectors
+    const uint2 *sel;     // LDS: 16 {gather, scatter} selectors
+    uint32_t selmask;     // byte offset of w's entry: w & selmask
     const uint8_t *rule;  // LDS: rule tables, byte addressed
     uint32_t W1, W2;      // word-space thresholds (w <= W1: first table ...)
     uint32_t B1, B2, B3;  // byte offsets of the three rule tables to use
@@ -78,17 +79,18 @@ __host__ __device__ inline ActionSplit split_actions(uint32_t T1, uint32_t T2)
     return s;
 }
 
-// Builds the selector table (2 KB) and the rule tables (3*Sp*Sp u16, plus
-// the three selection outcomes when `prob`: 6*Sp*Sp) in LDS with the
-// workgroup's threads.  dom: 32 dominance masks (LDS or global).
-// Von Neumann: bits 0-1 of the block word pick the edge, bit 2 the
-// orientation.  Moore: bits 0-2 pick one of eight pair slots (the four
-// edges, then the diagonals (A,D), (B,C) twice each), bit 3 the orientation.
+// Builds the selector table (16 entries, 128 B) and the rule tables
+// (3*Sp*Sp u16, plus the three selection outcomes when `prob`: 6*Sp*Sp) in
+// LDS with the workgroup's threads.  dom: 32 dominance masks (LDS or
+// global).  Entry i = (w >> 3) & 15 of block word w.  Von Neumann: bits 0-1
+// of i pick the edge, bit 2 the orientation (entries 8-15 unused).  Moore:
+// bits 0-2 pick one of eight pair slots (the four edges, then the diagonals
+// (A,D), (B,C) twice each), bit 3 the orientation.
 __device__ inline void build_quad_luts(uint2 *sel, uint16_t *rule, uint32_t Sp,
                                        const uint32_t *dom, bool moore,
                                        bool prob = false)
 {
-    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) {
+    for (uint32_t i = threadIdx.x; i < 16; i += blockDim.x) {
         const uint32_t e = moore ? (i & 7u) : (i & 3u);
         const uint32_t o = moore ? (i >> 3) & 1u : (i >> 2) & 1u;
         // pair sites as byte positions of B = [A, B, C, D]
@@ -145,9 +147,17 @@ __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo,
     return __builtin_amdgcn_perm(hi, lo, sel);
 }
 
+// The selector pair of block word w.
+template <class Ctx>
+__device__ __forceinline__ uint2 sel_of(uint32_t w, const Ctx &c)
+{
+    return *reinterpret_cast<const uint2 *>(
+        reinterpret_cast<const uint8_t *>(c.sel) + (w & c.selmask));
+}
+
 // One block: B = [A, B, C, D] -> updated dword, given the block's selector
-// pair s = sel[w & 0xFF] (loaded by the caller, so that the lookups of a
-// quad can be issued early).
+// pair s = sel_of(w) (loaded by the caller, so that the lookups of a quad
+// can be issued early).
 template <class Ctx>
 __device__ __forceinline__ uint32_t block_update_sel(uint32_t B, uint32_t w,
                                                      uint2 s, const Ctx &c)
@@ -177,7 +187,7 @@ template <class Ctx>
 __device__ __forceinline__ uint32_t block_update(uint32_t B, uint32_t w,
                                                  const Ctx &c)
 {
-    return block_update_sel(B, w, c.sel[w & 0xFFu], c);
+    return block_update_sel(B, w, sel_of(w, c), c);
 }
 
 // The four selector pairs of a quad's words.
@@ -191,7 +201,7 @@ __device__ __forceinline__ QuadSel quad_sel(const Words &w, const Ctx &c)
     QuadSel q;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-        q.s[k] = c.sel[w.w[k] & 0xFFu];
+        q.s[k] = sel_of(w.w[k], c);
     return q;
 }
 
