@@ -44,6 +44,7 @@ L2_PROB_RSU = ("tests/test_oracle_chain.py::"
                "test_L2_probabilistic_rsu_matches_exact_chain")
 L4_PROB = ("tests/test_oracle_chain.py::"
            "test_L4_probabilistic_one_pass_matches_exact_block_law")
+RNG_INIT = "tests/test_rng_artefacts.py::test_init_has_no_spatial_correlation"
 
 # (name, text in escg_oracle.c, planted replacement, pins that must fail)
 MUTANTS = [
@@ -96,6 +97,11 @@ MUTANTS = [
     # initial lattice never empty (species 1..S only)
     ("init_never_empty",
      "(uint64_t)(S + 1u)) >> 32);", "(uint64_t)S) >> 32) + 1u;", [INIT]),
+    # initial lattice: one draw shared by sites four columns apart (a
+    # spatial artefact of the kind the paper's Metal generator showed)
+    ("init_draws_shared_between_sites",
+     "draw(seed, (uint32_t)(n >> 2), 0u, TAG_INIT << 8",
+     "draw(seed, (uint32_t)(n >> 3), 0u, TAG_INIT << 8", [RNG_INIT]),
     # counts drop the last species
     ("counts_drop_last_species",
      "if (grid[n] <= S)", "if (grid[n] < S)", [CONSERVE]),

@@ -25,8 +25,8 @@ def _extinction(args):
 
 
 def _densities(args):
-    which, L, M, T, rep, nbhd = args
-    job = O.Job(L, 3, O.circulant_matrix(3, [1]), eps_from_mobility(M, L),
+    which, L, M, T, rep, nbhd, S, K = args
+    job = O.Job(L, S, O.circulant_matrix(S, K), eps_from_mobility(M, L),
                 seed=2, replica=rep, nbhd=nbhd)
     g = job.init()
     f = O.o2_run if which == 2 else O.o1_run
@@ -47,14 +47,18 @@ def test_extinction_probability_o1_vs_o2():
     assert ks_2samp(r1[:, 1], r2[:, 1]).pvalue > 1e-4
 
 
-@pytest.mark.parametrize("nbhd", [4, 8])
-def test_mean_densities_o1_vs_o2(nbhd):
-    L, M, T, R = 64, 1e-5, 200, 240
+@pytest.mark.parametrize("S,K,nbhd", [(3, (1,), 4), (3, (1,), 8),
+                                      (5, (1, 3), 4), (5, (1, 3), 8)],
+                         ids=["rps-vn", "rps-moore", "rpsls-vn",
+                              "rpsls-moore"])
+def test_mean_densities_o1_vs_o2(S, K, nbhd):
+    """RPS and RPSLS (i beats i+1 and i+3), von Neumann and Moore."""
+    L, M, T, R = 64, 1e-5, 200, 600
     with Pool(8) as p:
         d2 = np.array(p.map(_densities,
-                            [(2, L, M, T, i, nbhd) for i in range(R)]))
+                            [(2, L, M, T, i, nbhd, S, K) for i in range(R)]))
         d1 = np.array(p.map(_densities,
-                            [(1, L, M, T, i, nbhd) for i in range(R)]))
+                            [(1, L, M, T, i, nbhd, S, K) for i in range(R)]))
     diff = np.abs(d1.mean(0) - d2.mean(0))
     se = np.sqrt(d1.var(0, ddof=1) / R + d2.var(0, ddof=1) / R)
     assert (diff <= np.maximum(4 * se, 0.005)).all(), (diff, se)
