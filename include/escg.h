@@ -96,12 +96,17 @@ typedef int32_t escg_status;
  *             (0: automatic; else a multiple of 64, 64..1024, EINVAL
  *             otherwise).
  *   wg_per_cu escg_batch_run only: resident workgroups per compute unit
- *             (0: as many as fit; else 1..8, capped by what fits). */
+ *             (0: as many as fit; else 1..8, capped by what fits).
+ *   max_wgs   escg_batch_run and escg_step_batch (read from their first
+ *             job): at most this many workgroups in one launch (0: as many
+ *             as the device keeps resident), so that work on another stream
+ *             keeps the remaining CUs. */
 typedef struct escg_launch {
     uint32_t route;
     uint32_t tile_h, tile_w;
     uint32_t threads;
     uint32_t wg_per_cu;
+    uint32_t max_wgs;
 } escg_launch;
 
 /* Job parameters.  Rates are named by role; only their ratios matter (the
@@ -269,12 +274,24 @@ escg_status escg_batch_run(uint32_t n, const escg_params *h_params,
                            void *stream);
 
 /* Advances n independent jobs, job j by h_n_mcs[j] MCS from absolute MCS
- * h_mcs0[j], with one launch per MCS for all jobs together: the tiles of
- * every job still running form one grid, so lattices too small to fill the
- * GPU on their own share it.  This is the step of the paper's overall loop
- * (Algorithm "Overall ESCG Loop", N elementary steps per MCS) for a set of
- * simulations at once; each job's result equals escg_step_mcs on that job
- * alone, byte for byte.
+ * h_mcs0[j], all jobs together.  This is the step of the paper's overall
+ * loop (Algorithm "Overall ESCG Loop", N elementary steps per MCS) for a set
+ * of simulations at once; each job's result equals escg_step_mcs on that
+ * job alone, byte for byte.  Two paths, chosen by h_params[0].launch.route:
+ *   0 or ESCG_ROUTE_PERSISTENT: persistent launches holding several jobs:
+ *             every tile of every job stays in LDS for all of the job's MCS
+ *             and exchanges halos with its own job's tiles only; jobs are
+ *             packed whole into launches of at most max_wgs workgroups (or
+ *             what the device keeps resident), longest chunk first, one
+ *             launch after the other on the stream; a job with more tiles
+ *             than one launch holds runs per MCS as below.  A launch's tiles
+ *             wait only for each other and never for other work, so they
+ *             all become resident even while other streams' kernels hold
+ *             CUs for a while; a wait that exceeds its bound (seconds) is
+ *             reported by escg_async_status as ESCG_ETIMEOUT.
+ *   ESCG_ROUTE_TILED: one launch per MCS for all jobs: the tiles of every
+ *             job still running form one grid, so lattices too small to
+ *             fill the GPU on their own share it.
  *   h_params[n]      job parameters; every L must be a multiple of 8 and
  *                    >= 16 (ESCG_EUNSUPPORTED otherwise, nothing enqueued,
  *                    escg_last_error() names the job)
@@ -283,15 +300,18 @@ escg_status escg_batch_run(uint32_t n, const escg_params *h_params,
  *   h_mcs0[n], h_n_mcs[n]  start MCS and number of MCS per job (0: untouched)
  * No counts are recorded (escg_densities reads a lattice afterwards).
  * n == 0 returns ESCG_OK and touches nothing; with n > 0 a NULL array gives
- * ESCG_EINVAL.
- * Scratch: one ping-pong lattice per job, stream-ordered. */
+ * ESCG_EINVAL.  escg_last_route() afterwards: ESCG_ROUTE_PERSISTENT if any
+ * persistent launch was made, else ESCG_ROUTE_TILED.
+ * Scratch (stream-ordered): per persistent launch a job table, two exchange
+ * slots per tile and an abort word per job; per-MCS path: one ping-pong
+ * lattice per job. */
 escg_status escg_step_batch(uint32_t n, const escg_params *h_params,
                             uint8_t *const *h_lattices, const uint32_t *h_mcs0,
                             const uint32_t *h_n_mcs, void *stream);
 
-/* Which kernel path the calling thread's last escg_step_mcs with n_mcs > 0
- * or escg_run_until_extinction enqueued (ESCG_ROUTE_*; 0 before any such
- * call).  When the persistent path is planned but its cooperative launch is
+/* Which kernel path the calling thread's last escg_step_mcs with n_mcs > 0,
+ * escg_run_until_extinction or escg_step_batch enqueued (ESCG_ROUTE_*; 0
+ * before any such call).  When the persistent path is planned but its cooperative launch is
  * refused, the call falls back to per-MCS launches and escg_last_error()
  * says why. */
 uint32_t escg_last_route(void);

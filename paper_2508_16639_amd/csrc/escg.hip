@@ -559,20 +559,29 @@ __device__ uint32_t g_async_error;
 
 struct TiledArgs {
     uint8_t *lattice;   // in/out
-    uint32_t *exch;     // 2 * T * slot_dwords exchange area, slots pre-tagged
+    uint32_t *exch;     // exchange slot 0 of this job (T * slot_dwords), slot
+                        // 1 at exch + xstride; tags pre-set (exch_tag)
     uint32_t *abort;    // 1 word, zeroed
     uint32_t *counts;   // rows (n+1)*(S+1) with rows 1..n zeroed, or null
     uint64_t seed;
     TileGeom G;
     uint32_t S, T1, T2, replica, mcs0, n_mcs, spin_limit, moore;
+    uint32_t xstride;   // dwords from slot 0 to slot 1 of the exchange area
+    uint32_t wg0;       // multi-job launches: first workgroup of this job
     const uint32_t *ab;   // selection thresholds (global) or null
     uint32_t dom[32];
 };
 
+// One tile of one job for all of its MCS: load the tile and halo into LDS,
+// then per MCS the four passes, the tagged publish of the border strips, the
+// interior counts (overlapped with the first halo loads) and the halo
+// gather; finally store the interior.  `a` is the job (kernel argument or a
+// global table entry: its fields are read once into registers).
 // kList: the quads of a pass by TileList (else TileWalk); one walk per
 // instantiation keeps the other's code and registers out of the MCS loop.
 template <bool kPacked, bool kProb, bool kList>
-__global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
+__device__ __forceinline__ void persistent_tile(const TiledArgs &a,
+                                                uint32_t tile)
 {
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ LdsTables<kPacked ? 8 : 32> TB;
@@ -582,23 +591,25 @@ __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
     uint8_t *lat = smem;
     const TileGeom G = a.G;
     const uint32_t tid = threadIdx.x, S = a.S;
-    const uint32_t T = G.TY * G.TX;
-    // XCD-aware: workgroups are dealt round-robin to the 8 XCDs, so give
-    // each XCD a contiguous band of tiles (neighbours share an L2).
-    const uint32_t b = blockIdx.x;
-    const uint32_t tile = (T % 8u == 0) ? (b & 7u) * (T >> 3) + (b >> 3) : b;
     const uint32_t ty = tile / G.TX, tx = tile - (tile / G.TX) * G.TX;
-    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
-    const uint32_t sd = G.slot_dwords();
+    const uint64_t seed = a.seed;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const uint32_t sd = G.slot_dwords(), xs = a.xstride;
+    uint8_t *const glat = a.lattice;
+    uint32_t *const exch = a.exch;
+    uint32_t *const abort_w = a.abort;
+    uint32_t *const counts = a.counts;
+    const uint32_t mcs0 = a.mcs0, n_mcs = a.n_mcs, replica = a.replica;
+    const uint32_t spin_limit = a.spin_limit;
 
     if (tid == 0)
         s_misc[0] = 0;
     for (uint32_t i = tid; i < 8 * kCountSlots; i += blockDim.x)
         s_part[i] = 0;
-    tile_load(lat, a.lattice, G, ty, tx);
+    tile_load(lat, glat, G, ty, tx);
     setup_tables(TB, a.dom, a.moore != 0, kProb ? a.ab : nullptr);
     const auto qc = make_quad_ctx<kProb>(TB, a.T1, a.T2); // after a barrier
-    const HaloPlan HP = halo_plan(a.exch, G, ty, tx);
+    const HaloPlan HP = halo_plan(exch, G, ty, tx);
 
     bool aborted = false;
     const TileWalk W = tile_walk(G, ty, tx);
@@ -607,21 +618,22 @@ __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
         TL = tile_list(G, ty, tx);
     // (a plain loop: the same loop written as a lambda taking the walk
     // measured 10 % slower per MCS on mid-size lattices)
-    for (uint32_t t = 0; t < a.n_mcs; ++t) {
+    for (uint32_t t = 0; t < n_mcs; ++t) {
         if constexpr (kList)
-            tile_mcs_list(lat, G, TL, a.mcs0 + t, a.replica, k0, k1, qc);
+            tile_mcs_list(lat, G, TL, mcs0 + t, replica, k0, k1, qc);
         else
-            tile_mcs(lat, G, W, a.mcs0 + t, a.replica, k0, k1, qc);
+            tile_mcs(lat, G, W, mcs0 + t, replica, k0, k1, qc);
         // publish, count and gather touch disjoint parts of the region:
         // border strips and interior are read, only the halo is written
         const uint32_t e = t + 1, slot = exch_slot(e), tag = exch_tag(e);
-        tile_publish(lat, a.exch + (size_t)(slot * T + tile) * sd, G, tag);
+        tile_publish(lat, exch + (size_t)slot * xs + (size_t)tile * sd, G,
+                     tag);
         // the tags replace flags: each halo word is awaited on its own; the
         // counts run while the first halo loads are in flight
         const uint32_t st = tile_gather(
-            lat, a.exch, HP, G, ty, tx, slot * T * sd, tag, a.abort,
-            a.spin_limit, [&] {
-                if (a.counts) {
+            lat, exch, HP, G, ty, tx, slot * xs, tag, abort_w, spin_limit,
+            [&] {
+                if (counts) {
                     if (kPacked)
                         tile_count_sums(lat, G, S, s_part);
                     else
@@ -630,14 +642,14 @@ __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
             });
         if (st) {
             if (st == 2) {
-                xstore(a.abort, 1u);
+                xstore(abort_w, 1u);
                 atomicOr(&g_async_error, 1u);
             }
             s_misc[0] = 1;
         }
         __syncthreads();
-        if (a.counts) {
-            uint32_t *row = a.counts + (size_t)(t + 1) * (S + 1);
+        if (counts) {
+            uint32_t *row = counts + (size_t)(t + 1) * (S + 1);
             if constexpr (kPacked) {
                 if (tid < 64) // one wave; the slots are next used 4 barriers on
                     tile_count_flush(s_part, S, G.TH * G.TW, row);
@@ -652,7 +664,50 @@ __global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
         }
     }
     if (!aborted)
-        tile_store(lat, a.lattice, G, ty, tx);
+        tile_store(lat, glat, G, ty, tx);
+}
+
+// XCD-aware tile of workgroup b of a job with T tiles: workgroups are dealt
+// round-robin to the 8 XCDs, so when T % 8 == 0 each XCD gets a contiguous
+// band of tiles (neighbours share an L2).  b counts from a multiple of 8.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t T)
+{
+    return (T % 8u == 0) ? (b & 7u) * (T >> 3) + (b >> 3) : b;
+}
+
+// All MCS of one large lattice in one cooperative launch (one workgroup per
+// tile).
+template <bool kPacked, bool kProb, bool kList>
+__global__ __launch_bounds__(1024) void tiled_persistent_kernel(TiledArgs a)
+{
+    persistent_tile<kPacked, kProb, kList>(a, xcd_tile(blockIdx.x,
+                                                       a.G.TY * a.G.TX));
+}
+
+// Several large lattices in one launch: job j owns workgroups
+// [wg0_j, wg0_j + T_j) (wg0_j a multiple of 8 when T_j is; workgroups in
+// the gaps exit at once) and runs its own MCS count.  The tiles of a job
+// wait only for each other, and the launch holds no more workgroups than
+// the device keeps resident at once, so every tile becomes resident even
+// while other kernels hold CUs for a while (they never wait for this one).
+template <bool kPacked, bool kProb, bool kList>
+__global__ __launch_bounds__(1024) void tiled_persistent_multi_kernel(
+    const TiledArgs *__restrict__ jobs, uint32_t njobs)
+{
+    const uint32_t b = blockIdx.x;
+    uint32_t lo = 0, hi = njobs;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (jobs[mid].wg0 <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const TiledArgs &a = jobs[lo];
+    const uint32_t T = a.G.TY * a.G.TX, local = b - a.wg0;
+    if (local >= T)
+        return;
+    persistent_tile<kPacked, kProb, kList>(a, xcd_tile(local, T));
 }
 
 // One MCS of a large lattice per launch with the tile phases above: each
@@ -1544,6 +1599,7 @@ escg_status run_tiled_persistent(const escg_params *p, const Derived &d,
     a.lattice = lattice;
     a.exch = reinterpret_cast<uint32_t *>(scr);
     a.abort = a.exch + 2 * slot_area;
+    a.xstride = (uint32_t)slot_area;
     a.counts = counts;
     a.seed = p->seed;
     a.G = G;
@@ -1709,6 +1765,284 @@ escg_status run_until_persistent(const escg_params *p, const Derived &d,
 }
 
 bool aligned4(const void *p) { return ((uintptr_t)p & 3u) == 0; }
+
+// ---------------------------------------------------------------------------
+// Several large lattices in one persistent launch (escg_step_batch)
+// ---------------------------------------------------------------------------
+
+// Workgroup size of the multi-job persistent kernel: one workgroup per CU
+// (the kernel's registers allow no second one), the same for every job of a
+// launch.
+constexpr uint32_t kMultiThreads = 1024;
+
+// Tile plan of a job inside a multi-job launch: the shape with the least
+// workgroup time T * (4 * busiest-SIMD quad load per pass + a fixed
+// exchange and barrier share per MCS), so large jobs take few, large tiles
+// and leave CUs for other jobs.
+TiledPlan plan_multi_uncached(uint32_t L, uint32_t S, const PlanHints &h)
+{
+    TiledPlan best;
+    if (L % 8 != 0 || L < 16)
+        return best;
+    const DeviceInfo di = device_info();
+    const size_t lds_max = di.lds_max ? di.lds_max : 65536;
+    const uint32_t nt = kMultiThreads;
+    const bool forced = h.TH != 0 && valid_shape(L, h.TH, h.TW);
+    if (h.TH != 0 && !forced)
+        return best;
+    double best_cost = 1e300;
+    for (uint32_t TW = 8; TW <= L; TW += 8) {
+        if (L % TW || (forced && TW != h.TW))
+            continue;
+        for (uint32_t TH = 4; TH <= L; TH += 2) {
+            if (L % TH || (forced && TH != h.TH))
+                continue;
+            const TileGeom G{L, TH, TW, L / TH, L / TW};
+            const size_t lds = G.region_bytes();
+            if (lds + tiled_static_lds_bytes(S) + 64 > lds_max ||
+                G.TW / 4 > nt)
+                continue;
+            const bool list = tile_list_fits(G, nt);
+            if (!list && tiled_threads(G, nt) == 0)
+                continue;
+            const double T = (double)G.TY * G.TX;
+            const double cost =
+                T * (4.0 * walk_simd_load(G, nt, list) + 24.0);
+            if (cost < best_cost) {
+                best_cost = cost;
+                best.ok = true;
+                best.G = G;
+                best.threads = nt;
+                best.lds = lds;
+                best.list = list;
+            }
+        }
+    }
+    return best;
+}
+
+TiledPlan plan_multi(uint32_t L, uint32_t S, const PlanHints &h)
+{
+    static std::mutex mu;
+    static std::map<PlanKey, TiledPlan> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const PlanKey key = std::make_tuple(dev, L, S <= 7, h.TH, h.TW, 0u);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end())
+            return it->second;
+    }
+    const TiledPlan plan = plan_multi_uncached(L, S <= 7 ? 7u : 31u, h);
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = plan;
+    return plan;
+}
+
+const void *persistent_multi_kernel(bool packed, bool prob, bool list)
+{
+    static const void *const fns[8] = {
+        (const void *)tiled_persistent_multi_kernel<false, false, false>,
+        (const void *)tiled_persistent_multi_kernel<false, false, true>,
+        (const void *)tiled_persistent_multi_kernel<false, true, false>,
+        (const void *)tiled_persistent_multi_kernel<false, true, true>,
+        (const void *)tiled_persistent_multi_kernel<true, false, false>,
+        (const void *)tiled_persistent_multi_kernel<true, false, true>,
+        (const void *)tiled_persistent_multi_kernel<true, true, false>,
+        (const void *)tiled_persistent_multi_kernel<true, true, true>};
+    return fns[(packed ? 4 : 0) + (prob ? 2 : 0) + (list ? 1 : 0)];
+}
+
+// Workgroups that one multi-job launch may hold: what the device keeps
+// resident at once for the kernel (with `lds` bytes of dynamic LDS), capped
+// by the caller's max_wgs (0: no cap).
+uint32_t multi_capacity(const void *fn, size_t lds, uint32_t max_wgs)
+{
+    allow_dynamic_lds(fn, lds);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn,
+                                                     kMultiThreads, lds) !=
+        hipSuccess)
+        (void)hipGetLastError();
+    const DeviceInfo di = device_info();
+    uint32_t cap = (uint32_t)std::max(0, per_cu) * (uint32_t)std::max(0, di.cus);
+    if (max_wgs)
+        cap = std::min(cap, max_wgs);
+    return cap;
+}
+
+// One multi-job launch of the jobs `idx` (same kernel instantiation; their
+// padded workgroup ranges already fit `cap`): job table, exchange areas and
+// abort words in one stream-ordered allocation.
+escg_status launch_multi(const std::vector<uint32_t> &idx,
+                         const std::vector<TiledPlan> &plans,
+                         const escg_params *P, uint8_t *const *lats,
+                         const uint32_t *mcs0, const uint32_t *nm, bool packed,
+                         bool prob, bool list, hipStream_t st)
+{
+    const uint32_t m = (uint32_t)idx.size();
+    const uint32_t Sp = packed ? 8u : 32u, abw = 2u * Sp * Sp;
+    std::vector<TiledArgs> tbl(m);
+    std::vector<uint32_t> ab_all;
+    if (prob)
+        ab_all.resize((size_t)m * abw);
+    size_t slot_dw = 0, lds = 0;
+    uint32_t wg = 0;
+    for (uint32_t i = 0; i < m; ++i) {
+        const uint32_t j = idx[i];
+        const escg_params *p = &P[j];
+        const TiledPlan &pl = plans[j];
+        const Derived d = derive(p);
+        if (prob) {
+            const std::vector<uint32_t> ab =
+                selection_thresholds(p, d.T1, d.T2, Sp);
+            std::copy(ab.begin(), ab.end(), ab_all.begin() + (size_t)i * abw);
+        }
+        const uint32_t T = pl.G.TY * pl.G.TX;
+        if (T % 8u == 0)
+            wg = (wg + 7u) & ~7u; // XCD bands (xcd_tile) need wg0 % 8 == 0
+        TiledArgs &a = tbl[i];
+        std::memset(&a, 0, sizeof(a));
+        a.lattice = lats[j];
+        a.seed = p->seed;
+        a.G = pl.G;
+        a.S = p->S;
+        a.T1 = d.T1;
+        a.T2 = d.T2;
+        a.replica = p->replica;
+        a.mcs0 = mcs0[j];
+        a.n_mcs = nm[j];
+        a.spin_limit = 1u << 22; // polls (seconds), then abort with an error
+        a.moore = (p->flags & ESCG_FLAG_MOORE) ? 1u : 0u;
+        a.wg0 = wg;
+        for (int q = 0; q < 32; ++q)
+            a.dom[q] = p->dom[q];
+        a.xstride = (uint32_t)slot_dw; // offset of slot 0, set below
+        slot_dw += (size_t)T * pl.G.slot_dwords();
+        wg += T;
+        lds = std::max(lds, pl.lds);
+    }
+    // layout: table | thresholds | slot 0 of every job | slot 1 of every
+    // job | abort words (64 B apart)
+    const size_t tbl_bytes = (sizeof(TiledArgs) * m + 255) & ~(size_t)255;
+    const size_t ab_bytes = (ab_all.size() * 4 + 255) & ~(size_t)255;
+    const size_t slot_bytes = (slot_dw * 4 + 255) & ~(size_t)255;
+    const size_t total = tbl_bytes + ab_bytes + 2 * slot_bytes + 64 * (size_t)m;
+    uint8_t *dev = nullptr;
+    if (hipMallocAsync((void **)&dev, total, st) != hipSuccess)
+        return ESCG_ENOMEM;
+    uint32_t *slot0 = reinterpret_cast<uint32_t *>(dev + tbl_bytes + ab_bytes);
+    uint32_t *abort0 =
+        reinterpret_cast<uint32_t *>(dev + tbl_bytes + ab_bytes + 2 * slot_bytes);
+    for (uint32_t i = 0; i < m; ++i) {
+        TiledArgs &a = tbl[i];
+        a.exch = slot0 + a.xstride;
+        a.xstride = (uint32_t)(slot_bytes / 4);
+        a.abort = abort0 + 16 * i;
+        a.ab = prob ? reinterpret_cast<const uint32_t *>(dev + tbl_bytes) +
+                          (size_t)i * abw
+                    : nullptr;
+    }
+    // slot 0 tagged 0, slot 1 tagged 1: neither matches its first use
+    launch_fill(slot0, slot_bytes / 4, exch_tag(2) ^ 0x80808080u, st);
+    launch_fill(slot0 + slot_bytes / 4, slot_bytes / 4,
+                exch_tag(1) ^ 0x80808080u, st);
+    launch_fill(abort0, 16 * (size_t)m, 0, st);
+    escg_status s = ESCG_OK;
+    if (hipMemcpyAsync(dev, tbl.data(), sizeof(TiledArgs) * m,
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
+        (prob && hipMemcpyAsync(dev + tbl_bytes, ab_all.data(),
+                                ab_all.size() * 4, hipMemcpyHostToDevice,
+                                st) != hipSuccess))
+        s = last_hip(hipGetLastError());
+    if (s == ESCG_OK) {
+        const void *fn = persistent_multi_kernel(packed, prob, list);
+        allow_dynamic_lds(fn, lds);
+        const TiledArgs *tp = reinterpret_cast<const TiledArgs *>(dev);
+        uint32_t nj = m;
+        void *args[] = {&tp, &nj};
+        s = last_hip(hipLaunchKernel(fn, dim3(wg), dim3(kMultiThreads), args,
+                                     lds, st));
+    }
+    (void)hipFreeAsync(dev, st);
+    return s;
+}
+
+// The persistent part of escg_step_batch: jobs with a multi-job plan run in
+// launches of whole jobs, grouped by kernel instantiation, each launch
+// holding at most `cap` workgroups; jobs left over (no plan, or more tiles
+// than one launch holds) are returned in `rest`.
+escg_status step_batch_persistent(uint32_t n, const escg_params *P,
+                                  uint8_t *const *lats, const uint32_t *mcs0,
+                                  const uint32_t *nm, uint32_t max_wgs,
+                                  hipStream_t st, std::vector<uint32_t> &rest,
+                                  bool &launched)
+{
+    launched = false;
+    std::vector<TiledPlan> plans(n);
+    std::vector<uint32_t> keys(n, 8u);
+    for (uint32_t j = 0; j < n; ++j) {
+        if (nm[j] == 0)
+            continue;
+        plans[j] = plan_multi(P[j].L, P[j].S, plan_hints(&P[j]));
+        if (!plans[j].ok) {
+            rest.push_back(j);
+            continue;
+        }
+        keys[j] = (P[j].S <= 7 ? 4u : 0u) + (P[j].dom_prob ? 2u : 0u) +
+                  (plans[j].list ? 1u : 0u);
+    }
+    for (uint32_t key = 0; key < 8; ++key) {
+        const bool packed = key & 4u, prob = key & 2u, list = key & 1u;
+        // longest chunks first, so a launch's jobs end at similar times
+        std::vector<uint32_t> idx;
+        size_t lds = 0;
+        for (uint32_t j = 0; j < n; ++j)
+            if (keys[j] == key) {
+                idx.push_back(j);
+                lds = std::max(lds, plans[j].lds);
+            }
+        if (idx.empty())
+            continue;
+        std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) {
+            return nm[a] > nm[b];
+        });
+        const uint32_t cap = multi_capacity(
+            persistent_multi_kernel(packed, prob, list), lds, max_wgs);
+        std::vector<uint32_t> cur;
+        uint32_t wg = 0;
+        for (size_t k = 0; k <= idx.size(); ++k) {
+            uint32_t T = 0, need = 0;
+            if (k < idx.size()) {
+                const TileGeom &G = plans[idx[k]].G;
+                T = G.TY * G.TX;
+                if (T > cap) {
+                    rest.push_back(idx[k]);
+                    continue;
+                }
+                need = ((T % 8u == 0) ? ((wg + 7u) & ~7u) : wg) + T;
+            }
+            if (k == idx.size() || need > cap) {
+                if (!cur.empty()) {
+                    const escg_status s = launch_multi(
+                        cur, plans, P, lats, mcs0, nm, packed, prob, list, st);
+                    if (s != ESCG_OK)
+                        return s;
+                    launched = true;
+                }
+                cur.clear();
+                wg = 0;
+                if (k == idx.size())
+                    break;
+                need = T;
+            }
+            cur.push_back(idx[k]);
+            wg = need;
+        }
+    }
+    return ESCG_OK;
+}
 
 // The path of a single job (escg_step_mcs, escg_run_until_extinction) from
 // its launch choice: forced, or automatic (persistent for L % 8 == 0 and
@@ -2141,6 +2475,23 @@ escg_status escg_step_batch(uint32_t n, const escg_params *h_params,
         if (spans[j].first < spans[j - 1].second)
             return ESCG_EINVAL; // lattices overlap
     hipStream_t st = S_(stream);
+    // persistent multi-job launches unless the per-MCS path is asked for;
+    // jobs they cannot take keep their MCS count for the per-MCS launches
+    std::vector<uint32_t> nm(h_n_mcs, h_n_mcs + n);
+    bool persistent = false;
+    if (h_params[0].launch.route != ESCG_ROUTE_TILED) {
+        std::vector<uint32_t> rest;
+        const escg_status s = step_batch_persistent(
+            n, h_params, h_lattices, h_mcs0, h_n_mcs,
+            h_params[0].launch.max_wgs, st, rest, persistent);
+        if (s != ESCG_OK)
+            return s;
+        std::vector<uint32_t> left(n, 0u);
+        for (uint32_t j : rest)
+            left[j] = h_n_mcs[j];
+        nm = left;
+    }
+    h_n_mcs = nm.data();
     for (int packed = 1; packed >= 0; --packed) {
         // jobs of this kernel instantiation, longest chunk first, so the jobs
         // still running at step k are a prefix of the table
@@ -2250,7 +2601,7 @@ escg_status escg_step_batch(uint32_t n, const escg_params *h_params,
         if (s != ESCG_OK)
             return s;
     }
-    g_last_route = ESCG_ROUTE_TILED;
+    g_last_route = persistent ? ESCG_ROUTE_PERSISTENT : ESCG_ROUTE_TILED;
     return ESCG_OK;
 }
 
@@ -2369,8 +2720,10 @@ escg_status escg_batch_run(uint32_t n, const escg_params *h_params,
     if (ln.wg_per_cu)
         per_cu = std::min(per_cu, (int)ln.wg_per_cu);
     const DeviceInfo di = device_info();
-    const uint32_t grid =
+    uint32_t grid =
         std::min<uint32_t>(n, (uint32_t)std::max(1, di.cus) * per_cu);
+    if (ln.max_wgs)
+        grid = std::min(grid, ln.max_wgs);
     const JobDev *aj = d_jobs;
     const uint32_t *ao = d_order;
     uint32_t an = n;

@@ -41,7 +41,7 @@ class EscgError(RuntimeError):
 class CLaunch(C.Structure):
     _fields_ = [("route", C.c_uint32), ("tile_h", C.c_uint32),
                 ("tile_w", C.c_uint32), ("threads", C.c_uint32),
-                ("wg_per_cu", C.c_uint32)]
+                ("wg_per_cu", C.c_uint32), ("max_wgs", C.c_uint32)]
 
 
 class CParams(C.Structure):
@@ -145,6 +145,7 @@ class Params:
     tile: Optional[Tuple[int, int]] = None  # (TH, TW) of the tiled paths
     threads: int = 0         # workgroup size cap, multiple of 64
     wg_per_cu: int = 0       # batch kernel: resident workgroups per CU
+    max_wgs: int = 0         # batch_run / step_batch: workgroups per launch
 
     def c(self) -> CParams:
         p = CParams()
@@ -169,11 +170,12 @@ class Params:
             (int(self.tile[0]), int(self.tile[1])) if self.tile else (0, 0))
         p.launch.threads = int(self.threads)
         p.launch.wg_per_cu = int(self.wg_per_cu)
+        p.launch.max_wgs = int(self.max_wgs)
         return p
 
     def with_launch(self, **kw) -> "Params":
         """A copy with other launch choices (route, tile, threads,
-        wg_per_cu); the job itself is unchanged."""
+        wg_per_cu, max_wgs); the job itself is unchanged."""
         return dataclasses.replace(self, **kw)
 
 
@@ -350,8 +352,10 @@ def batch_run(params: Sequence[Params], offsets, lattices, max_mcs,
 def step_batch(params: Sequence[Params], lattices, mcs0, n_mcs,
                stream=None) -> None:
     """Advances each job i (``lattices[i]``: its uint8 device tensor of
-    L*L sites) by ``n_mcs[i]`` MCS from MCS ``mcs0[i]``, all jobs together,
-    one launch per MCS.  Every L must be a multiple of 8 (>= 16)."""
+    L*L sites) by ``n_mcs[i]`` MCS from MCS ``mcs0[i]``, all jobs together:
+    persistent launches holding several jobs, or one launch per MCS when the
+    first job's route is "tiled".  Every L must be a multiple of 8
+    (>= 16)."""
     n = len(params)
     assert len(lattices) == n and len(mcs0) == n and len(n_mcs) == n
     arr = (CParams * max(n, 1))()

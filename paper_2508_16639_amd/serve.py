@@ -10,9 +10,11 @@ arrive while an iteration runs join at the next iteration boundary.
 
 Work within an iteration overlaps on the device: all active jobs small
 enough for one workgroup's LDS advance together in one persistent batched
-launch (one workgroup per job), while the larger jobs advance together on a
-second stream with one tiled launch per MCS whose grid holds the tiles of
-all of them.  Because every random draw
+launch (one workgroup per job, on a share of the CUs), while the larger
+jobs advance together on a second stream in persistent launches that each
+hold the tiles of several jobs (every tile resident in LDS for the job's
+whole chunk, halos exchanged within its job) on the remaining CUs.
+Because every random draw
 is keyed by (seed, replica, MCS, pass, site), a job's result does not depend
 on its co-runners, on chunking or on admission time: it is byte-identical to
 the job run alone.
@@ -22,6 +24,7 @@ scheduler testable with a CPU executor and an injected clock.
 """
 from __future__ import annotations
 
+import dataclasses
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -193,7 +196,8 @@ class DeviceExecutor:
     """Runs jobs on the current GPU through the C ABI."""
 
     def __init__(self, torch, escg, n_streams: int = 4,
-                 keep_lattices: bool = False):
+                 keep_lattices: bool = False, small_share: float = 0.25,
+                 large_route: str = "persistent"):
         self.torch = torch
         self.escg = escg
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
@@ -201,6 +205,12 @@ class DeviceExecutor:
         self.small_max = {}
         self.keep = keep_lattices
         self.final_lattices: Dict[int, np.ndarray] = {}
+        self.cus = torch.cuda.get_device_properties(0).multi_processor_count
+        # workgroups (one per CU) the small jobs' batch may hold while large
+        # jobs run beside it; the large jobs' persistent launches get the
+        # rest, so both kernels' workgroups are resident together
+        self.small_share = small_share
+        self.large_route = large_route  # "persistent" or "tiled" (per MCS)
 
     def _params(self, req):
         return self.escg.Params(L=req.L, S=req.S,
@@ -242,6 +252,10 @@ class DeviceExecutor:
         self.batch_stream.wait_stream(cur)
         for s in self.streams:
             s.wait_stream(cur)
+        small_wgs = 0
+        if small and large:
+            small_wgs = min(len(small),
+                            max(1, int(self.cus * self.small_share)))
         # small jobs: one persistent batched launch per kernel instantiation
         # (S <= 7 and S > 7 tables), one after the other on the batch stream
         res_keep = []
@@ -249,6 +263,10 @@ class DeviceExecutor:
                       [w for w in small if w[1].S > 7]):
             if not group:
                 continue
+            if small_wgs:
+                group[0] = (dict(group[0][0],
+                                 p=group[0][0]["p"].with_launch(
+                                     max_wgs=small_wgs)),) + group[0][1:]
             # lattices live in separate tensors: offsets from the lowest
             base = min(h["lat"].data_ptr() for h, _, _, _ in group)
             top = max(h["lat"].data_ptr() + r.L * r.L for h, r, _, _ in group)
@@ -268,8 +286,10 @@ class DeviceExecutor:
                 ev.record()
                 done.append(ev)
             self._res = res_keep  # alive until the iteration completes
-        # large jobs with a tile plan advance together, one launch per MCS
-        # for all of them; any others run alone on the remaining streams
+        # large jobs with a tile plan advance together in persistent
+        # launches of several jobs each (or one launch per MCS for all of
+        # them with large_route "tiled"); any others run alone on the
+        # remaining streams
         tiled = [w for w in large if w[1].L % 8 == 0 and w[1].L >= 16]
         alone = [w for w in large if not (w[1].L % 8 == 0 and w[1].L >= 16)]
         if len(tiled) == 1 and not small and not alone:
@@ -278,8 +298,11 @@ class DeviceExecutor:
             # about twice as fast per MCS as one launch per MCS
             alone, tiled = tiled, []
         if tiled:
+            first = tiled[0][0]["p"].with_launch(
+                route=self.large_route,
+                max_wgs=self.cus - small_wgs if small_wgs else 0)
             with torch.cuda.stream(self.streams[0]):
-                escg.step_batch([h["p"] for h, _, _, _ in tiled],
+                escg.step_batch([first] + [h["p"] for h, _, _, _ in tiled[1:]],
                                 [h["lat"] for h, _, _, _ in tiled],
                                 [m0 for _, _, m0, _ in tiled],
                                 [n for _, _, _, n in tiled])
@@ -361,22 +384,39 @@ def plain_serving(torch, escg, requests, clock=time.perf_counter,
     return st
 
 
-def bench_serving(torch, escg, workloads, n_jobs: int = 2000):
-    """The Poisson serving workload through the server and through plain
-    one-at-a-time serving, on the same GPU."""
-    reqs = workloads.serving_requests(n=n_jobs)
-    ex = DeviceExecutor(torch, escg)
-    st, _ = Scheduler(ex).run(reqs)
+def bench_serving(torch, escg, workloads, n_jobs: int = 2000,
+                  rates=(200.0, 400.0, 800.0), plain: bool = True):
+    """The Poisson serving workload through the server at each arrival rate
+    (the first is the workload's 200 jobs/s), at saturation (every request
+    at t = 0: the server's capacity), and through plain one-at-a-time
+    serving at the first rate, on the same GPU."""
+    out = {"workload": f"{n_jobs} jobs, Poisson, S in {{3,5}}, "
+                       "L in {100,200,400,800,1600}, M log-uniform "
+                       "[1e-6,1e-3], MCS uniform [500,5000]",
+           "by_rate": {}}
+    base = None
+    for rate in rates:
+        reqs = workloads.serving_requests(n=n_jobs, rate_per_s=rate)
+        st, _ = Scheduler(DeviceExecutor(torch, escg)).run(reqs)
+        escg.async_status()
+        out["by_rate"][f"{rate:g}"] = st.summary()
+        if base is None:
+            base = reqs
+    reqs = [dataclasses.replace(r, arrival_s=0.0) for r in base]
+    st, _ = Scheduler(DeviceExecutor(torch, escg)).run(reqs)
     escg.async_status()
-    plain = plain_serving(torch, escg, reqs)
-    s = st.summary()
-    pl = plain.summary()
-    return {
-        "workload": f"{n_jobs} jobs, Poisson 200/s, S in {{3,5}}, "
-                    "L in {100,200,400,800,1600}, M log-uniform [1e-6,1e-3], "
-                    "MCS uniform [500,5000]",
-        "server": s,
-        "plain": pl,
-        "speedup_jobs_per_s": s["jobs_per_s"] / pl["jobs_per_s"]
-        if pl["jobs_per_s"] else None,
-    }
+    out["capacity"] = st.summary()
+    out["server"] = out["by_rate"][f"{rates[0]:g}"]
+    if plain:
+        pl = plain_serving(torch, escg, base).summary()
+        out["plain"] = pl
+        out["speedup_jobs_per_s"] = (out["server"]["jobs_per_s"] /
+                                     pl["jobs_per_s"]
+                                     if pl["jobs_per_s"] else None)
+        out["capacity_vs_plain"] = (out["capacity"]["jobs_per_s"] /
+                                    pl["jobs_per_s"]
+                                    if pl["jobs_per_s"] else None)
+        out["plain_note"] = ("plain serving is saturated at the first rate "
+                             "(its jobs/s is its capacity); at higher rates "
+                             "its queue only grows")
+    return out

@@ -156,7 +156,8 @@ def test_moore_differs_from_von_neumann_on_gpu():
     assert not np.array_equal(a, b)
 
 
-def test_moore_step_batch_and_batch_run_match_oracle():
+@pytest.mark.parametrize("route", ["tiled", "persistent"])
+def test_moore_step_batch_and_batch_run_match_oracle(route):
     specs = [(16, 3, [1], 3), (136, 5, [1, 3], 2), (64, 13, [1, 2, 5], 1)]
     ps, js, lats, g0s = [], [], [], []
     for i, (L, S, K, n) in enumerate(specs):
@@ -166,7 +167,9 @@ def test_moore_step_batch_and_batch_run_match_oracle():
         js.append(j)
         g0s.append(g0)
         lats.append(dev(g0))
+    ps[0] = ps[0].with_launch(route=route)
     escg.step_batch(ps, lats, [4] * len(specs), [s[3] for s in specs])
+    assert escg.last_route() == route
     for (L, S, K, n), j, g0, lat in zip(specs, js, g0s, lats):
         ref = g0.copy()
         O.o2_run(j, ref, 4, n)
@@ -252,7 +255,8 @@ def test_probabilities_equal_to_matrix_reproduce_deterministic_bytes(route):
     assert np.array_equal(a, b) and np.array_equal(ca, cb)
 
 
-def test_probabilistic_batches_and_run_until_match_oracle():
+@pytest.mark.parametrize("route", ["tiled", "persistent"])
+def test_probabilistic_batches_and_run_until_match_oracle(route):
     # a batch mixing deterministic and probabilistic jobs, both kernel
     # instantiations; the batched per-MCS step; run-until on the
     # persistent kernel
@@ -289,7 +293,9 @@ def test_probabilistic_batches_and_run_until_match_oracle():
         js.append(j)
         g0s.append(g0)
         lats.append(dev(g0))
+    ps[0] = ps[0].with_launch(route=route)
     escg.step_batch(ps, lats, [2] * len(specs), [s[3] for s in specs])
+    assert escg.last_route() == route
     for (L, D, prob, n), j, g0, lat in zip(specs, js, g0s, lats):
         ref = g0.copy()
         O.o2_run(j, ref, 2, n)
@@ -342,13 +348,19 @@ def test_imported_dominance_bit_exact(name, D, L, route):
     assert np.array_equal(c, rc)
 
 
-def test_step_batch_matches_oracle_per_job():
+@pytest.mark.parametrize("route,max_wgs", [("tiled", 0), ("persistent", 0),
+                                           ("persistent", 24),
+                                           ("persistent", 9)])
+def test_step_batch_matches_oracle_per_job(route, max_wgs):
     # jobs of both kernel instantiations (S <= 7 and S > 7), different sides,
-    # chunk lengths (0, odd and even: the state ends in the lattice or in
-    # the scratch buffer) and start MCS
+    # chunk lengths (0, odd and even: the per-MCS path's state ends in the
+    # lattice or in the scratch buffer) and start MCS; the persistent path
+    # packs whole jobs into launches of at most max_wgs workgroups (24: the
+    # jobs split over several launches; 9: the L = 800 job has more tiles
+    # than a launch holds and runs per MCS)
     specs = [(16, 3, [1], 3, 0), (64, 5, [1, 3], 0, 5), (136, 8, [1, 2, 5], 2, 9),
              (64, 13, [1, 2, 5], 1, 2), (200, 3, [1], 4, 100), (24, 2, [1], 5, 1),
-             (800, 5, [1, 3], 2, 7)]
+             (800, 5, [1, 3], 2, 7), (416, 3, [1], 7, 3)]
     ps, js, lats, g0s = [], [], [], []
     for i, (L, S, K, n, m0) in enumerate(specs):
         p, j = pair(L, S, K, 0.7 + i, 1.0, 1.0, seed=50 + i, replica=i)
@@ -357,11 +369,44 @@ def test_step_batch_matches_oracle_per_job():
         js.append(j)
         g0s.append(g0)
         lats.append(dev(g0))
+    ps[0] = ps[0].with_launch(route=route, max_wgs=max_wgs)
     escg.step_batch(ps, lats, [s[4] for s in specs], [s[3] for s in specs])
+    assert escg.last_route() == route
     for (L, S, K, n, m0), j, g0, lat in zip(specs, js, g0s, lats):
         ref = g0.copy()
         O.o2_run(j, ref, m0, n)
         assert np.array_equal(host(lat), ref), (L, S, n)
+    escg.async_status()
+
+
+def test_step_batch_persistent_serving_sizes():
+    """The server's large jobs (L = 800 and 1600, S = 3 and 5, chunks of
+    different lengths from different start MCS) in persistent launches:
+    each job equals the oracle, and the same job run alone on the
+    persistent single-job kernel."""
+    specs = [(1600, 5, [1, 3], 24, 100), (800, 3, [1], 31, 0),
+             (1600, 3, [1], 17, 7), (800, 5, [1, 3], 40, 500),
+             (800, 3, [1], 2, 3)]
+    ps, js, lats, g0s = [], [], [], []
+    for i, (L, S, K, n, m0) in enumerate(specs):
+        ex = float(escg.eps_from_mobility(10.0 ** (-3 - i % 3), L))
+        p, j = pair(L, S, K, ex, seed=900 + i, replica=i)
+        g0 = random_lattice(L, S, seed=i, domain=4)
+        ps.append(p)
+        js.append(j)
+        g0s.append(g0)
+        lats.append(dev(g0))
+    escg.step_batch(ps, lats, [s[4] for s in specs], [s[3] for s in specs])
+    assert escg.last_route() == "persistent"
+    for (L, S, K, n, m0), p, j, g0, lat in zip(specs, ps, js, g0s, lats):
+        got = host(lat)
+        alone, _ = gpu_step(p.with_launch(route="persistent"), g0, m0, n,
+                            want_counts=False)
+        assert np.array_equal(got, alone), (L, S, n)
+        ref = g0.copy()
+        O.o2_run(j, ref, m0, n, want_counts=False)
+        assert np.array_equal(got, ref), (L, S, n)
+    escg.async_status()
 
 
 def test_step_batch_rejects_lattices_without_tile_plan():

@@ -38,9 +38,11 @@ def alone_gpu(r):
     return lat.cpu().numpy()
 
 
-def test_server_results_equal_alone_runs():
+@pytest.mark.parametrize("large_route", ["persistent", "tiled"])
+def test_server_results_equal_alone_runs(large_route):
     reqs = requests()
-    ex = DeviceExecutor(torch, escg, keep_lattices=True)
+    ex = DeviceExecutor(torch, escg, keep_lattices=True,
+                        large_route=large_route)
     st, jobs = Scheduler(ex, ServerConfig(work_per_iter=2e6,
                                           min_chunk=3)).run(reqs)
     escg.async_status()
@@ -66,3 +68,26 @@ def test_server_under_small_hbm_budget_queues_instead_of_dropping():
     st, jobs = Scheduler(ex, cfg).run(reqs)
     assert st.completed == len(reqs) and st.failed == 0
     assert st.peak_footprint <= cfg.hbm_budget
+
+
+def test_server_mixes_wide_and_narrow_species_tables():
+    """Small jobs with S > 7 (wide rule tables, a smaller LDS limit) and
+    S <= 7 at L = 400 in the same iterations, beside large jobs (L = 800,
+    1600) in persistent launches: each result equals the job alone."""
+    reqs = []
+    for i, (L, S, K) in enumerate([(400, 3, (1,)), (256, 13, (1, 2, 5)),
+                                   (400, 5, (1, 3)), (1600, 5, (1, 3)),
+                                   (200, 13, (1, 2, 5)), (800, 3, (1,)),
+                                   (400, 3, (1,)), (1600, 3, (1,))]):
+        M = 10.0 ** (-3 - i % 3)
+        reqs.append(Request(job_id=i, arrival_s=0.002 * i, L=L, S=S, K=K,
+                            M=M, ex=M * L * L / 2, mcs=9 + 5 * i,
+                            seed=300 + i))
+    ex = DeviceExecutor(torch, escg, keep_lattices=True)
+    st, jobs = Scheduler(ex, ServerConfig(work_per_iter=4e7,
+                                          min_chunk=4)).run(reqs)
+    escg.async_status()
+    assert st.completed == len(reqs) and st.failed == 0
+    for r in reqs:
+        assert np.array_equal(ex.final_lattices[r.job_id], alone_gpu(r)), \
+            r.job_id
