@@ -34,6 +34,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -124,6 +126,13 @@ def batch(args, torch, escg, workloads):
     res = torch.empty(n * escg.BATCH_RESULT_WORDS, dtype=torch.int32,
                       device="cuda")
     reps = max(1, min(3, args.steps))
+    from paper_2508_16639_amd import autotune
+    sides = tuple(sorted(set(int(x) for x in tab.L)))
+    tuned = autotune.lookup(torch, "batch", sides, 3)
+    launch = {"autotuned": tuned is not None,
+              **autotune.launch_choice(tuned)}
+    if tuned:
+        params[0] = params[0].with_launch(**autotune.launch_choice(tuned))
     escg.batch_run(params, offs, buf, tab.max_mcs,
                    escg.STOP_FIRST_EXTINCTION, True, res)
     torch.cuda.synchronize()
@@ -135,42 +144,78 @@ def batch(args, torch, escg, workloads):
     wall = (time.perf_counter() - t0) / reps
     r = res.cpu().numpy().reshape(n, escg.BATCH_RESULT_WORDS)
     su = float((tab.L.astype(float) ** 2 * r[:, 1]).sum())
-    # plain: one job at a time (init + run until extinction + sync), on the
-    # first `k` replicas of the same table
-    k = 32
+    # plain: one job at a time (init + run until extinction + sync), on a
+    # seeded random sample of the same table
+    k = min(n, 128)
+    pick = np.random.default_rng(12345).choice(n, size=k, replace=False)
     one = torch.empty(256 * 256, dtype=torch.uint8, device="cuda")
     out = torch.empty(6, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    su_plain = 0.0
-    for i in range(k):
-        q = params[i]
+    times, su_plain = [], 0.0
+    for i in pick:
+        q = params[int(i)]
+        t1 = time.perf_counter()
         escg.init(q, one)
         escg.run_until_extinction(q, one, 0, int(tab.max_mcs[i]),
                                   escg.STOP_FIRST_EXTINCTION, out)
         torch.cuda.synchronize()
+        times.append(time.perf_counter() - t1)
         su_plain += float(q.L) ** 2 * int(out[1].item())
-    plain_wall = time.perf_counter() - t0
+    times = np.asarray(times)
+    mean, se = times.mean(), times.std(ddof=1) / np.sqrt(k)
+    plain_jps = 1.0 / mean
+    lo, hi = 1.0 / (mean + 1.96 * se), 1.0 / max(mean - 1.96 * se, 1e-12)
     return {
         "workload": "4096 RPS replicas, L in {64,128,192,256}, "
                     "M log-uniform [1e-6,1e-3], first extinction or 20 L MCS",
         "jobs_per_s": n / wall,
         "site_updates_per_s": su / wall,
+        "su_per_job": su / n,
         "seconds": wall,
         "extinct_fraction": float(r[:, 0].mean()),
-        "plain_jobs_per_s": k / plain_wall,
-        "plain_site_updates_per_s": su_plain / plain_wall,
-        "plain_sample": f"first {k} replicas, one at a time on one stream",
-        "speedup_vs_plain": (n / wall) / (k / plain_wall),
+        "launch": launch,
+        "plain_jobs_per_s": plain_jps,
+        "plain_jobs_per_s_95ci": [lo, hi],
+        "plain_site_updates_per_s": su_plain / times.sum(),
+        "plain_sample": f"{k} replicas drawn at random (seed 12345) from the "
+                        f"table, one at a time on one stream (init, run "
+                        f"until extinction, synchronise); 95 % interval "
+                        f"from the sample's per-job times",
+        "speedup_vs_plain": (n / wall) / plain_jps,
+        "speedup_vs_plain_95ci": [(n / wall) / hi, (n / wall) / lo],
     }
 
 
 def serving(args, torch, escg, workloads):
-    try:
-        from paper_2508_16639_amd import serve
-    except ImportError:
-        return None
+    from paper_2508_16639_amd import serve
     return serve.bench_serving(torch, escg, workloads)
+
+
+def rps512(args, torch, escg, workloads):
+    """The L = 512 RPS workload (10,000 MCS, counts every MCS): init and
+    the whole run per repetition, on the route the library picks."""
+    w = workloads.RPS512
+    p = escg.Params(L=w.L, S=w.S, dom=escg.circulant_dom(w.S, w.K), ex=w.ex,
+                    sel=w.sel, rep=w.rep, seed=w.seed, replica=w.replica)
+    lat = torch.empty(w.L * w.L, dtype=torch.uint8, device="cuda")
+    cnt = torch.empty((w.mcs + 1) * (w.S + 1), dtype=torch.int32,
+                      device="cuda")
+    escg.init(p, lat)
+    escg.step_mcs(p, lat, 0, w.mcs, cnt)
+    torch.cuda.synchronize()
+    reps = max(1, min(5, args.steps))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        escg.init(p, lat)
+        escg.step_mcs(p, lat, 0, w.mcs, cnt)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    c = cnt.cpu().numpy().reshape(w.mcs + 1, w.S + 1)
+    assert (c.sum(1) == w.L * w.L).all()
+    return {"workload": "rps_L512_M1e-4_10000mcs (counts every MCS)",
+            "site_updates_per_s": float(w.L) ** 2 * w.mcs / wall,
+            "ms_per_run": wall * 1e3, "route": escg.last_route(),
+            "reps": reps}
 
 
 def host_cpu() -> str:
@@ -234,7 +279,7 @@ def cpu_context(w):
     with mp.Pool(cores) as pool:
         su = sum(pool.map(_o2_replica, tasks))
     dall = time.perf_counter() - t0
-    return {"o1_one_thread": {"value": float(w.L) ** 2 * n1 / d1,
+    res = {"o1_one_thread": {"value": float(w.L) ** 2 * n1 / d1,
                               "unit": "site-updates/s",
                               "sample": f"L={w.L} RPSLS, {n1} MCS, "
                                         f"{d1:.1f} s"},
@@ -243,7 +288,58 @@ def cpu_context(w):
                              "sample": f"{cores} replicas of L={L} RPSLS "
                                        f"x {n} MCS, one per process, "
                                        f"{dall:.1f} s"},
-            "host": host_cpu()}
+           "host": host_cpu()}
+    return res
+
+
+def _o2_job(args):
+    import oracle as O
+    L, S, K, ex, seed, replica, n = args
+    job = O.Job(L, S, O.circulant_matrix(S, K), ex, seed=seed,
+                replica=replica)
+    g = job.init()
+    O.o2_run(job, g, 0, n, want_counts=False)
+    return L * L * n
+
+
+def cpu_jobs(workloads, batch_su_per_job):
+    """Jobs/s of the oracle on every host core for the batched-replica and
+    serving workloads: site-updates/s measured on all cores over a sample
+    of each workload's jobs (every job truncated to a few MCS, one job per
+    task), divided by the mean site-updates of one whole job (batch: from
+    the GPU run's stopping times; serving: from the request table)."""
+    import multiprocessing as mp
+    cores = max(1, min(16, os.cpu_count() or 1))
+    out = {"cores": cores, "kind": "oracle"}
+    tab = workloads.batch_replicas()
+    rng = np.random.default_rng(7)
+    idx = rng.choice(len(tab), size=4 * cores, replace=False)
+    tasks = [(int(tab.L[i]), 3, [1], float(tab.ex[i]), tab.seed, int(i), 40)
+             for i in idx]
+    t0 = time.perf_counter()
+    with mp.Pool(cores) as pool:
+        su = sum(pool.map(_o2_job, tasks))
+    d = time.perf_counter() - t0
+    out["batch"] = {"site_updates_per_s": su / d,
+                    "jobs_per_s": su / d / batch_su_per_job
+                    if batch_su_per_job else None,
+                    "sample": f"{len(tasks)} random replicas x 40 MCS on "
+                              f"{cores} processes, {d:.1f} s"}
+    reqs = workloads.serving_requests()
+    mean_su = float(np.mean([float(r.L) ** 2 * r.mcs for r in reqs]))
+    pick = rng.choice(len(reqs), size=2 * cores, replace=False)
+    tasks = [(reqs[i].L, reqs[i].S, list(reqs[i].K), reqs[i].ex, reqs[i].seed,
+              0, 6) for i in pick]
+    t0 = time.perf_counter()
+    with mp.Pool(cores) as pool:
+        su = sum(pool.map(_o2_job, tasks))
+    d = time.perf_counter() - t0
+    out["serving"] = {"site_updates_per_s": su / d,
+                      "jobs_per_s": su / d / mean_su,
+                      "sample": f"{len(tasks)} random requests x 6 MCS on "
+                                f"{cores} processes, {d:.1f} s; mean job "
+                                f"{mean_su:.3g} site-updates"}
+    return out
 
 
 def main():
@@ -253,6 +349,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--skip-extras", action="store_true",
                     help="headline only (no batch, serving, cpu baseline)")
+    ap.add_argument("--leg", choices=["batch", "serving"], default=None,
+                    help="run only this leg (for profiling its kernels): "
+                         "the batched replicas, or the server at "
+                         "saturation (every request at t = 0)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="only run device-to-device copies of this many MiB "
                          "(reference for rocprofv3 byte counters) and exit")
@@ -279,6 +379,16 @@ def main():
         return
     escg.lib()
     w = workloads.RPSLS3200
+    if args.leg == "batch":
+        print(json.dumps({"batch": batch(args, torch, escg, workloads)}),
+              flush=True)
+        return
+    if args.leg == "serving":
+        from paper_2508_16639_amd import serve
+        r = serve.bench_serving(torch, escg, workloads, rates=(),
+                                plain=False)
+        print(json.dumps({"serving_capacity": r["capacity"]}), flush=True)
+        return
 
     from paper_2508_16639_amd import autotune
     p = escg.Params(L=w.L, S=w.S, dom=escg.circulant_dom(w.S, w.K), ex=w.ex,
@@ -330,6 +440,13 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "achieved_is": "algorithmic bytes (2 B per "
+                                    "site-update) / kernel time, not "
+                                    "measured HBM bandwidth",
+                     "measured_hbm_GBs": (traffic / (h["kernel_ms"] * 1e-3)
+                                          / 1e9 if traffic else None),
+                     "binding_limit": "alu (integer VALU issue; the lattice "
+                                      "stays in LDS, see the alu block)",
                      "kernel": "tiled_persistent_kernel",
                      "kernel_ms": h["kernel_ms"],
                      "algorithmic_bytes_per_launch":
@@ -344,12 +461,16 @@ def main():
         log("[bench] batch (4096 replicas)")
         out["batch"] = batch(args, torch, escg, workloads)
         log(f"[bench] batch {out['batch']['jobs_per_s']:.1f} jobs/s")
+        log("[bench] rps L=512 (10000 MCS, counts every MCS)")
+        out["rps_L512"] = rps512(args, torch, escg, workloads)
         log("[bench] serving")
         out["serving"] = serving(args, torch, escg, workloads)
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(w)
         log("[bench] cpu context (O1, all-core O2)")
         out["cpu_context"] = cpu_context(w)
+        out["cpu_context"]["jobs"] = cpu_jobs(
+            workloads, out["batch"].get("su_per_job"))
     print(json.dumps(out), flush=True)
 
 

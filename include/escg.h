@@ -316,10 +316,12 @@ escg_status escg_step_batch(uint32_t n, const escg_params *h_params,
  * says why. */
 uint32_t escg_last_route(void);
 
-/* The tile shape and workgroup size the persistent (persistent != 0) or
- * per-MCS tiled path would use for job p (its L, S and launch choices) on
- * the current device.  EUNSUPPORTED if that path cannot run the job, EINVAL
- * for invalid parameters or NULL outputs. */
+/* The tile shape and workgroup size that a path would use for job p (its
+ * L, S and launch choices) on the current device: persistent = 1 the
+ * single-job persistent kernel, 2 a multi-job persistent launch of
+ * escg_step_batch, 0 the per-MCS tiled kernel.  EUNSUPPORTED if that path
+ * cannot run the job, EINVAL for invalid parameters, persistent > 2 or
+ * NULL outputs. */
 escg_status escg_tile_plan(const escg_params *p, uint32_t persistent,
                            uint32_t *TH, uint32_t *TW, uint32_t *threads);
 

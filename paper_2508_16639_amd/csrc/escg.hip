@@ -1972,12 +1972,13 @@ escg_status launch_multi(const std::vector<uint32_t> &idx,
 // The persistent part of escg_step_batch: jobs with a multi-job plan run in
 // launches of whole jobs, grouped by kernel instantiation, each launch
 // holding at most `cap` workgroups; jobs left over (no plan, or more tiles
-// than one launch holds) are returned in `rest`.
+// than one launch holds) are returned in `rest`.  dry_run: plan only (the
+// same `rest`, nothing enqueued).
 escg_status step_batch_persistent(uint32_t n, const escg_params *P,
                                   uint8_t *const *lats, const uint32_t *mcs0,
                                   const uint32_t *nm, uint32_t max_wgs,
                                   hipStream_t st, std::vector<uint32_t> &rest,
-                                  bool &launched)
+                                  bool &launched, bool dry_run)
 {
     launched = false;
     std::vector<TiledPlan> plans(n);
@@ -2024,7 +2025,7 @@ escg_status step_batch_persistent(uint32_t n, const escg_params *P,
                 need = ((T % 8u == 0) ? ((wg + 7u) & ~7u) : wg) + T;
             }
             if (k == idx.size() || need > cap) {
-                if (!cur.empty()) {
+                if (!cur.empty() && !dry_run) {
                     const escg_status s = launch_multi(
                         cur, plans, P, lats, mcs0, nm, packed, prob, list, st);
                     if (s != ESCG_OK)
@@ -2415,9 +2416,12 @@ escg_status escg_tile_plan(const escg_params *p, uint32_t persistent,
         return s;
     if (!TH || !TW || !threads)
         return ESCG_EINVAL;
+    if (persistent > 2)
+        return ESCG_EINVAL;
     const PlanHints h = plan_hints(p);
-    const TiledPlan tp =
-        persistent ? plan_tiled(p->L, p->S, h) : plan_step(p->L, p->S, h);
+    const TiledPlan tp = persistent == 2   ? plan_multi(p->L, p->S, h)
+                         : persistent == 1 ? plan_tiled(p->L, p->S, h)
+                                           : plan_step(p->L, p->S, h);
     if (!tp.ok)
         return ESCG_EUNSUPPORTED;
     *TH = tp.G.TH;
@@ -2451,7 +2455,6 @@ escg_status escg_step_batch(uint32_t n, const escg_params *h_params,
         return ESCG_OK;
     if (!h_params || !h_lattices || !h_mcs0 || !h_n_mcs)
         return ESCG_EINVAL;
-    std::vector<TiledPlan> plans(n);
     std::vector<std::pair<uintptr_t, uintptr_t>> spans(n);
     for (uint32_t j = 0; j < n; ++j) {
         const escg_params *p = &h_params[j];
@@ -2460,13 +2463,6 @@ escg_status escg_step_batch(uint32_t n, const escg_params *h_params,
             return s;
         if (!h_lattices[j] || !aligned4(h_lattices[j]))
             return ESCG_EINVAL;
-        plans[j] = plan_step(p->L, p->S, plan_hints(p));
-        if (!plans[j].ok) {
-            std::snprintf(g_last_error, sizeof(g_last_error),
-                          "job %u: L = %u has no tile plan (needs L %% 8 == 0, "
-                          "L >= 16)", j, p->L);
-            return ESCG_EUNSUPPORTED;
-        }
         const uintptr_t a = reinterpret_cast<uintptr_t>(h_lattices[j]);
         spans[j] = {a, a + (uintptr_t)p->L * p->L};
     }
@@ -2476,20 +2472,52 @@ escg_status escg_step_batch(uint32_t n, const escg_params *h_params,
             return ESCG_EINVAL; // lattices overlap
     hipStream_t st = S_(stream);
     // persistent multi-job launches unless the per-MCS path is asked for;
-    // jobs they cannot take keep their MCS count for the per-MCS launches
+    // the jobs they cannot take keep their MCS count for per-MCS launches.
+    // Everything is planned before anything is enqueued.
+    const bool multi = h_params[0].launch.route != ESCG_ROUTE_TILED;
+    const uint32_t max_wgs = h_params[0].launch.max_wgs;
     std::vector<uint32_t> nm(h_n_mcs, h_n_mcs + n);
-    bool persistent = false;
-    if (h_params[0].launch.route != ESCG_ROUTE_TILED) {
+    if (multi) {
         std::vector<uint32_t> rest;
+        bool none = false;
         const escg_status s = step_batch_persistent(
-            n, h_params, h_lattices, h_mcs0, h_n_mcs,
-            h_params[0].launch.max_wgs, st, rest, persistent);
+            n, h_params, h_lattices, h_mcs0, h_n_mcs, max_wgs, st, rest, none,
+            true);
         if (s != ESCG_OK)
             return s;
         std::vector<uint32_t> left(n, 0u);
         for (uint32_t j : rest)
             left[j] = h_n_mcs[j];
         nm = left;
+    }
+    // per-MCS plans of the jobs left to that path (a tile shape asked for
+    // that only the persistent path can take yields to the planner's)
+    std::vector<TiledPlan> plans(n);
+    for (uint32_t j = 0; j < n; ++j) {
+        if (nm[j] == 0)
+            continue;
+        const escg_params *p = &h_params[j];
+        plans[j] = plan_step(p->L, p->S, plan_hints(p));
+        if (!plans[j].ok && p->launch.tile_h) {
+            PlanHints h = plan_hints(p);
+            h.TH = h.TW = 0;
+            plans[j] = plan_step(p->L, p->S, h);
+        }
+        if (!plans[j].ok) {
+            std::snprintf(g_last_error, sizeof(g_last_error),
+                          "job %u: L = %u has no tile plan (needs L %% 8 == 0, "
+                          "L >= 16)", j, p->L);
+            return ESCG_EUNSUPPORTED;
+        }
+    }
+    bool persistent = false;
+    if (multi) {
+        std::vector<uint32_t> rest;
+        const escg_status s = step_batch_persistent(
+            n, h_params, h_lattices, h_mcs0, h_n_mcs, max_wgs, st, rest,
+            persistent, false);
+        if (s != ESCG_OK)
+            return s;
     }
     h_n_mcs = nm.data();
     for (int packed = 1; packed >= 0; --packed) {

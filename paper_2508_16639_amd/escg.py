@@ -219,12 +219,14 @@ def batch_max_L(S: int = 3) -> int:
     return int(lib().escg_batch_max_L(int(S)))
 
 
-def tile_plan(p: Params, persistent: bool = True):
-    """(TH, TW, threads) the persistent (or per-MCS) tiled path would use
-    for job p with its launch choices, or None."""
+def tile_plan(p: Params, persistent=True):
+    """(TH, TW, threads) the persistent (True), per-MCS (False) or
+    multi-job persistent ("multi") tiled path would use for job p with its
+    launch choices, or None."""
     a, b, c = C.c_uint32(), C.c_uint32(), C.c_uint32()
     cp = p.c()
-    s = lib().escg_tile_plan(C.byref(cp), 1 if persistent else 0,
+    mode = 2 if persistent == "multi" else (1 if persistent else 0)
+    s = lib().escg_tile_plan(C.byref(cp), mode,
                              C.byref(a), C.byref(b), C.byref(c))
     if s == EUNSUPPORTED:
         return None
