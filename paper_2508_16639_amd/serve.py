@@ -112,8 +112,7 @@ class Scheduler:
         self.sleep = sleep
 
     def chunk_for(self, job: JobState) -> int:
-        L2 = float(job.req.L) ** 2
-        c = int(self.cfg.work_per_iter / L2)
+        c = int(self.cfg.work_per_iter / float(job.req.L) ** 2)
         c = max(self.cfg.min_chunk, min(self.cfg.max_chunk, c))
         return min(c, job.req.mcs - job.done_mcs)
 
@@ -196,8 +195,10 @@ class DeviceExecutor:
     """Runs jobs on the current GPU through the C ABI."""
 
     def __init__(self, torch, escg, n_streams: int = 4,
-                 keep_lattices: bool = False, small_share: float = 0.25,
-                 large_route: str = "persistent"):
+                 keep_lattices: bool = False,
+                 small_share: Optional[float] = 0.25,
+                 large_route: str = "persistent",
+                 small_L: Optional[int] = None, light_jobs: int = 128):
         self.torch = torch
         self.escg = escg
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
@@ -206,11 +207,24 @@ class DeviceExecutor:
         self.keep = keep_lattices
         self.final_lattices: Dict[int, np.ndarray] = {}
         self.cus = torch.cuda.get_device_properties(0).multi_processor_count
-        # workgroups (one per CU) the small jobs' batch may hold while large
-        # jobs run beside it; the large jobs' persistent launches get the
-        # rest, so both kernels' workgroups are resident together
+        # share of the CUs the small jobs' batch may hold while large jobs
+        # run beside it (None: the small jobs' share of the iteration's
+        # site-updates, which measured slower on the serving mix: 456
+        # against 482 jobs/s at saturation); the large jobs' persistent
+        # launches get the rest, so both kernels' workgroups are resident
+        # together
         self.small_share = small_share
         self.large_route = large_route  # "persistent" or "tiled" (per MCS)
+        # Largest side advanced whole in one workgroup's LDS (beside the
+        # LDS limit): None = adaptive: 256 while at most light_jobs jobs are
+        # active (an L = 400 lattice then runs faster as tiles on a few CUs:
+        # on the serving mix at 200 jobs/s p50 0.07 s and p99 0.17 s against
+        # 0.14 s and 0.29 s), no further limit when more are (one workgroup
+        # per small job packs the GPU better: 482 against 458 jobs/s at
+        # saturation).
+        self.small_L = small_L
+        self.light_jobs = light_jobs
+        self._limit = small_L if small_L is not None else 1 << 30
 
     def _params(self, req):
         return self.escg.Params(L=req.L, S=req.S,
@@ -218,13 +232,32 @@ class DeviceExecutor:
                                 ex=req.ex, sel=1.0, rep=1.0, seed=req.seed,
                                 replica=0)
 
+    def _tuned(self, p, kernel):
+        """p with the autotuned launch choices of `kernel` for its side
+        (tile shape of the multi-job or single-job persistent kernel);
+        unchanged if none are cached."""
+        from paper_2508_16639_amd import autotune
+        return autotune.apply(self.torch, p.with_launch(tile=None), kernel)
+
+    def share(self, small, large) -> float:
+        """Share of the CUs for the small jobs: fixed, or their share of the
+        iteration's site-updates (a small job runs on one workgroup, a large
+        job's tiles on one CU each, at about the same rate per CU)."""
+        if self.small_share is not None:
+            return self.small_share
+        ws = sum(float(r.L) ** 2 * n for _, r, _, n in small)
+        wl = sum(float(r.L) ** 2 * n for _, r, _, n in large)
+        return ws / (ws + wl) if ws + wl > 0 else 0.5
+
     def is_small(self, req) -> bool:
         """Whole lattice fits one workgroup's LDS beside the rule tables of
         its kernel instantiation (S <= 7 or S > 7; the two run as separate
-        batches, so an S > 7 job never shrinks the S <= 7 limit)."""
+        batches, so an S > 7 job never shrinks the S <= 7 limit) and is not
+        above small_L (larger lattices advance faster, per MCS, as tiles on
+        several CUs)."""
         if req.S not in self.small_max:
             self.small_max[req.S] = self.escg.batch_max_L(req.S)
-        return req.L <= self.small_max[req.S]
+        return req.L <= min(self.small_max[req.S], self._limit)
 
     def alloc(self, req):
         p = self._params(req)
@@ -245,6 +278,8 @@ class DeviceExecutor:
 
     def _advance(self, work):
         torch, escg = self.torch, self.escg
+        if self.small_L is None:
+            self._limit = 256 if len(work) <= self.light_jobs else 1 << 30
         small = [(h, r, m0, n) for h, r, m0, n in work if self.is_small(r)]
         large = [(h, r, m0, n) for h, r, m0, n in work if not self.is_small(r)]
         cur = torch.cuda.current_stream()
@@ -254,8 +289,8 @@ class DeviceExecutor:
             s.wait_stream(cur)
         small_wgs = 0
         if small and large:
-            small_wgs = min(len(small),
-                            max(1, int(self.cus * self.small_share)))
+            small_wgs = min(len(small), self.cus - 1,
+                            max(1, round(self.cus * self.share(small, large))))
         # small jobs: one persistent batched launch per kernel instantiation
         # (S <= 7 and S > 7 tables), one after the other on the batch stream
         res_keep = []
@@ -298,11 +333,14 @@ class DeviceExecutor:
             # about twice as fast per MCS as one launch per MCS
             alone, tiled = tiled, []
         if tiled:
-            first = tiled[0][0]["p"].with_launch(
+            kern = "multi" if self.large_route == "persistent" else "step"
+            ps = [self._tuned(h["p"], kern) for h, _, _, _ in tiled]
+            cap = self.cus - small_wgs
+            ps[0] = ps[0].with_launch(
                 route=self.large_route,
-                max_wgs=self.cus - small_wgs if small_wgs else 0)
+                max_wgs=cap if small_wgs else 0)
             with torch.cuda.stream(self.streams[0]):
-                escg.step_batch([first] + [h["p"] for h, _, _, _ in tiled[1:]],
+                escg.step_batch(ps,
                                 [h["lat"] for h, _, _, _ in tiled],
                                 [m0 for _, _, m0, _ in tiled],
                                 [n for _, _, _, n in tiled])
@@ -315,7 +353,8 @@ class DeviceExecutor:
         lone = len(alone) == 1 and not small and not tiled
         for i, (h, r, m0, n) in enumerate(alone):
             s = others[i % len(others)]
-            p = h["p"] if lone else h["p"].with_launch(route="tiled")
+            p = (self._tuned(h["p"], "persistent") if lone
+                 else h["p"].with_launch(route="tiled"))
             with torch.cuda.stream(s):
                 escg.step_mcs(p, h["lat"], m0, n, None)
                 ev = torch.cuda.Event()
@@ -394,7 +433,7 @@ def bench_serving(torch, escg, workloads, n_jobs: int = 2000,
                        "L in {100,200,400,800,1600}, M log-uniform "
                        "[1e-6,1e-3], MCS uniform [500,5000]",
            "by_rate": {}}
-    base = None
+    base = None if rates else workloads.serving_requests(n=n_jobs)
     for rate in rates:
         reqs = workloads.serving_requests(n=n_jobs, rate_per_s=rate)
         st, _ = Scheduler(DeviceExecutor(torch, escg)).run(reqs)
@@ -406,7 +445,12 @@ def bench_serving(torch, escg, workloads, n_jobs: int = 2000,
     st, _ = Scheduler(DeviceExecutor(torch, escg)).run(reqs)
     escg.async_status()
     out["capacity"] = st.summary()
-    out["server"] = out["by_rate"][f"{rates[0]:g}"]
+    if rates:
+        out["server"] = out["by_rate"][f"{rates[0]:g}"]
+    from paper_2508_16639_amd import autotune
+    out["large_jobs_autotuned"] = {
+        f"L={L},S<=7": autotune.lookup(torch, "multi", L, 3) is not None
+        for L in sorted({r.L for r in base if r.L > 400})}
     if plain:
         pl = plain_serving(torch, escg, base).summary()
         out["plain"] = pl
