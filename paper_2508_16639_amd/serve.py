@@ -225,6 +225,8 @@ class DeviceExecutor:
         self.small_L = small_L
         self.light_jobs = light_jobs
         self._limit = small_L if small_L is not None else 1 << 30
+        self._inflight = None  # event of the last queued iteration
+        self._res = []
 
     def _params(self, req):
         return self.escg.Params(L=req.L, S=req.S,
@@ -320,7 +322,9 @@ class DeviceExecutor:
                 ev = torch.cuda.Event()
                 ev.record()
                 done.append(ev)
-            self._res = res_keep  # alive until the iteration completes
+            # alive until the iteration completes (the host runs up to one
+            # iteration ahead, so keep the last two iterations' buffers)
+            self._res = (self._res + [res_keep])[-2:]
         # large jobs with a tile plan advance together in persistent
         # launches of several jobs each (or one launch per MCS for all of
         # them with large_route "tiled"); any others run alone on the
@@ -362,7 +366,17 @@ class DeviceExecutor:
                 done.append(ev)
         for ev in done:
             cur.wait_event(ev)
-        cur.synchronize()
+        # No host synchronisation per iteration: the next iteration's
+        # streams wait for this one through the current stream, and so does
+        # every later use of a freed lattice's memory (allocated on the
+        # current stream).  The host runs at most one iteration ahead: it
+        # waits for the previous iteration here while this one is queued.
+        # Results are read by collect(), which synchronises its own copy.
+        ev = torch.cuda.Event()
+        ev.record(cur)
+        if self._inflight is not None:
+            self._inflight.synchronize()
+        self._inflight = ev
 
     def collect(self, h, req):
         cnt = self.torch.empty(req.S + 1, dtype=self.torch.int32,
