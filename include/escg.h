@@ -278,7 +278,8 @@ escg_status escg_batch_run(uint32_t n, const escg_params *h_params,
  * loop (Algorithm "Overall ESCG Loop", N elementary steps per MCS) for a set
  * of simulations at once; each job's result equals escg_step_mcs on that
  * job alone, byte for byte.  Two paths, chosen by h_params[0].launch.route:
- *   0 or ESCG_ROUTE_PERSISTENT: persistent launches holding several jobs:
+ *   ESCG_ROUTE_TILED as below; any other value (0, ESCG_ROUTE_PERSISTENT,
+ *             ESCG_ROUTE_LDS): persistent launches holding several jobs:
  *             every tile of every job stays in LDS for all of the job's MCS
  *             and exchanges halos with its own job's tiles only; jobs are
  *             packed whole into launches of at most max_wgs workgroups (or
