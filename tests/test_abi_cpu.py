@@ -176,9 +176,17 @@ def test_launch_choices_travel_in_params():
     assert (c.launch.route, c.launch.tile_h, c.launch.tile_w,
             c.launch.threads, c.launch.wg_per_cu) == (0, 0, 0, 0, 0)
     q = p.with_launch(route="persistent", tile=(100, 400), threads=768,
-                      wg_per_cu=2).c()
+                      wg_per_cu=2, max_wgs=192).c()
     assert (q.launch.route, q.launch.tile_h, q.launch.tile_w,
-            q.launch.threads, q.launch.wg_per_cu) == (3, 100, 400, 768, 2)
+            q.launch.threads, q.launch.wg_per_cu,
+            q.launch.max_wgs) == (3, 100, 400, 768, 2, 192)
+    # the binding's struct has the header's six launch fields, in order
+    src = open(os.path.join(ROOT, "include", "escg.h")).read()
+    body = src[src.index("typedef struct escg_launch {"):
+               src.index("} escg_launch;")]
+    fields = re.findall(r"uint32_t ([a-z_, ]+);", body)
+    names = [n.strip() for f in fields for n in f.split(",")]
+    assert names == [f for f, _ in escg.CLaunch._fields_]
     assert p.route == "auto"                      # p itself is unchanged
     L = escg.lib()
     for name in ("escg_set_single_lds_max_L", "escg_set_persistent_min_L",
@@ -207,3 +215,10 @@ def test_invalid_launch_choices_rejected_before_device_work(field, value):
 def test_batch_limits_callable_without_gpu():
     assert escg.batch_max_L(0) == 0 and escg.batch_max_L(32) == 0
     assert escg.batch_max_L(3) >= escg.batch_max_L(31) > 0
+
+
+def test_tile_plan_kind_checked_before_device_work():
+    p = escg.Params(L=1600, S=3, dom=escg.circulant_dom(3, [1]), ex=1.0).c()
+    a, b, c = C.c_uint32(), C.c_uint32(), C.c_uint32()
+    assert escg.lib().escg_tile_plan(C.byref(p), 3, C.byref(a), C.byref(b),
+                                     C.byref(c)) == escg.EINVAL
