@@ -60,10 +60,13 @@ class ServerConfig:
     max_active: int = 512          # slots
     # Chunk of a job per iteration: work_per_iter site-updates, clamped to
     # [min_chunk, max_chunk] MCS.  The cap keeps iterations short when small
-    # lattices would take thousands of MCS (and a tiled batch as many
-    # launches), so large jobs are not held behind them: on the Poisson mix
-    # of L in {100..1600}, 1e9 / 500 served 198 jobs/s at p99 1.3 s where
-    # 4e8 / 2000 served 185 jobs/s at p99 4.1 s.
+    # lattices would take thousands of MCS, so large jobs are not held
+    # behind them.  On the serving mix (L in {100..1600}), measured as
+    # (p50, p99 at 200 jobs/s; p50, p99 at 400 jobs/s; jobs/s at
+    # saturation): 1e9 / 500: 0.085 s, 0.22 s; 0.15 s, 0.47 s; 489.
+    # 2e9 / 1000: 0.094 s, 0.17 s; 0.16 s, 0.44 s; 397.  3e9 / 1500: 0.11 s,
+    # 0.19 s; 0.18 s, 0.49 s; 503.  4e8 / 500: 0.16 s, 0.72 s; 0.50 s,
+    # 2.5 s; 385.
     work_per_iter: float = 1e9     # site-updates per job per iteration
     min_chunk: int = 8             # MCS
     max_chunk: int = 500           # MCS
