@@ -620,7 +620,8 @@ __device__ __forceinline__ void persistent_tile(const TiledArgs &a,
     // measured 10 % slower per MCS on mid-size lattices)
     for (uint32_t t = 0; t < n_mcs; ++t) {
         if constexpr (kList)
-            tile_mcs_list(lat, G, TL, mcs0 + t, replica, k0, k1, qc);
+            tile_mcs_list(lat, lat + G.region_bytes() + 8, G, TL, mcs0 + t,
+                          replica, k0, k1, qc);
         else
             tile_mcs(lat, G, W, mcs0 + t, replica, k0, k1, qc);
         // publish, count and gather touch disjoint parts of the region:
@@ -1159,6 +1160,13 @@ size_t static_lds_bytes(uint32_t S)
 }
 
 // The tiled kernels add the count slots (tile_count_sums) to the tables.
+// Dynamic LDS of a tiled kernel: the region, twice for the list walk (its
+// passes alternate between two copies).
+size_t tiled_lds_bytes(const TileGeom &G, bool list)
+{
+    return (list ? 2u : 1u) * (size_t)G.region_bytes();
+}
+
 size_t tiled_static_lds_bytes(uint32_t S)
 {
     return static_lds_bytes(S) + sizeof(uint32_t) * 8 * kCountSlots;
@@ -1415,9 +1423,14 @@ TiledPlan plan_tiled_uncached(uint32_t L, uint32_t S, const PlanHints &h)
             if (nt == 0)
                 continue;
             // the balanced list walk where it lowers the busiest SIMD's load
+            // (and its two region buffers fit)
             bool list = false;
             uint32_t load = walk_simd_load(G, nt, false);
-            for (uint32_t n = cap & ~255u; n >= 256; n -= 256) { // ties: more waves
+            const bool list_lds =
+                tiled_lds_bytes(G, true) + tiled_static_lds_bytes(S) + 64 <=
+                lds_max;
+            for (uint32_t n = cap & ~255u; n >= 256 && list_lds; n -= 256) {
+                // ties: more waves
                 if (!tile_list_fits(G, n) || G.TW / 4 > n)
                     continue;
                 const uint32_t l = walk_simd_load(G, n, true);
@@ -1428,10 +1441,11 @@ TiledPlan plan_tiled_uncached(uint32_t L, uint32_t S, const PlanHints &h)
                 }
             }
             const void *fn = persistent_kernel(S <= 7, false, list);
-            allow_dynamic_lds(fn, lds);
+            const size_t lds_used = tiled_lds_bytes(G, list);
+            allow_dynamic_lds(fn, lds_used);
             int per_cu = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nt,
-                                                             lds) != hipSuccess)
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &per_cu, fn, nt, lds_used) != hipSuccess)
                 (void)hipGetLastError();
             if (per_cu < 1 || T > (uint32_t)cus * (uint32_t)per_cu)
                 continue;
@@ -1442,7 +1456,7 @@ TiledPlan plan_tiled_uncached(uint32_t L, uint32_t S, const PlanHints &h)
                 best.ok = true;
                 best.G = G;
                 best.threads = nt;
-                best.lds = lds;
+                best.lds = lds_used;
                 best.list = list;
             }
         }
@@ -1802,7 +1816,10 @@ TiledPlan plan_multi_uncached(uint32_t L, uint32_t S, const PlanHints &h)
             if (lds + tiled_static_lds_bytes(S) + 64 > lds_max ||
                 G.TW / 4 > nt)
                 continue;
-            const bool list = tile_list_fits(G, nt);
+            const bool list =
+                tile_list_fits(G, nt) &&
+                tiled_lds_bytes(G, true) + tiled_static_lds_bytes(S) + 64 <=
+                    lds_max;
             if (!list && tiled_threads(G, nt) == 0)
                 continue;
             const double T = (double)G.TY * G.TX;
@@ -1813,7 +1830,7 @@ TiledPlan plan_multi_uncached(uint32_t L, uint32_t S, const PlanHints &h)
                 best.ok = true;
                 best.G = G;
                 best.threads = nt;
-                best.lds = lds;
+                best.lds = tiled_lds_bytes(G, list);
                 best.list = list;
             }
         }

@@ -14,7 +14,7 @@ namespace escg {
 // S <= 7 (values 0..7), SP = 32 any S <= 31.
 template <int SP>
 struct LdsTables {
-    uint2 sel[16];                // {gather, scatter} selectors, entry
+    uint2 sel[16];                // {weights, scatter} entries, entry
                                   // (w & selmask) / 8 of block word w
     uint32_t selmask;             // 0x38 (von Neumann) or 0x78 (Moore)
     uint16_t rule[6 * SP * SP];   // (x', y') per action (3 used without
@@ -147,9 +147,7 @@ __device__ inline QuadCtxT<kProb> make_quad_ctx(const LdsTables<SP> &T,
     qc.B3 = a.a3 * tb;
     qc.B2 = vgpr_copy(qc.B2); // the selects in block_update read B2, B3
     qc.B3 = vgpr_copy(qc.B3); // as vector operands
-    qc.dotw = (2u * SP) | (2u << 8);
     qc.ab = reinterpret_cast<const uint8_t *>(T.ab);
-    qc.abw = (4u * SP) | (4u << 8);
     qc.boff = SP * SP * 4u;
     qc.T1 = T1;
     qc.Bsel = 1u * tb;

@@ -7,16 +7,17 @@
 // For block word w:
 //   * w & 0x38 (von Neumann: bits 3-4 edge, bit 5 orientation) or w & 0x78
 //     (Moore: bits 3-5 pair, bit 6 orientation) is the byte offset of an
-//     8-byte LDS entry of two v_perm selectors: the gather selector moves
-//     (selected cell, neighbour) = (x, y) into bytes 0 and 1; the scatter
+//     8-byte LDS entry {weights, scatter}: `weights` holds 2*Sp in the byte
+//     of the selected cell x and 2 in the byte of its neighbour y (0 in the
+//     other two), so v_dot4_u32_u8(B, weights, base) is the address of the
+//     pair's rule entry straight from the block dword; the scatter v_perm
 //     selector writes (x', y') back into their places and keeps the other
 //     two sites.  The 8 (16) entries span 16 (32) dwords, so the 64 lanes'
 //     lookups never meet in a bank except on the same dword (a broadcast).
 //   * the action is picked by comparing w with thresholds pre-shifted into
 //     word space (u = w >> 8 < T  <=>  w <= (T << 8) - 1), which selects
-//     one of three rule tables;
-//   * the pair rule is one LDS lookup: rule[action][x][y] = x' | y' << 8,
-//     addressed by v_dot4_u32_u8(xy, {2*Sp, 2, 0, 0}, base).
+//     one of three rule tables (base);
+//   * the pair rule is one LDS lookup: rule[action][x][y] = x' | y' << 8.
 // Same species, exchange, selection and reproduction are all table entries,
 // so there are no branches and no equality test.
 #pragma once
@@ -33,15 +34,13 @@ namespace escg {
 template <bool kProb>
 struct QuadCtxT {
     static constexpr bool kProbabilistic = kProb;
-    const uint2 *sel;     // LDS: 16 {gather, scatter} selectors
+    const uint2 *sel;     // LDS: 16 {dot weights, scatter selector}
     uint32_t selmask;     // byte offset of w's entry: w & selmask
     const uint8_t *rule;  // LDS: rule tables, byte addressed
     uint32_t W1, W2;      // word-space thresholds (w <= W1: first table ...)
     uint32_t B1, B2, B3;  // byte offsets of the three rule tables to use
-    uint32_t dotw;        // {2*Sp, 2, 0, 0}
     // kProb only
     const uint8_t *ab;    // LDS: A table, then B table (Sp*Sp u32 each)
-    uint32_t abw;         // {4*Sp, 4, 0, 0}
     uint32_t boff;        // byte offset of the B table from A
     uint32_t T1;          // selection draws are u = T1 .. T2 - 1
     uint32_t Bsel;        // byte offset of the deterministic selection table
@@ -79,7 +78,8 @@ __host__ __device__ inline ActionSplit split_actions(uint32_t T1, uint32_t T2)
     return s;
 }
 
-// Builds the selector table (16 entries, 128 B) and the rule tables
+// Builds the selector table (16 entries {weights, scatter}, 128 B) and the
+// rule tables
 // (3*Sp*Sp u16, plus the three selection outcomes when `prob`: 6*Sp*Sp) in
 // LDS with the workgroup's threads.  dom: 32 dominance masks (LDS or
 // global).  Entry i = (w >> 3) & 15 of block word w.  Von Neumann: bits 0-1
@@ -107,13 +107,14 @@ __device__ inline void build_quad_luts(uint2 *sel, uint16_t *rule, uint32_t Sp,
                            : (e & 1u) ? 2u
                                       : 3u;
         const uint32_t cell = o ? s : f, nbr = o ? f : s;
-        const uint32_t gather = cell | (nbr << 8) | 0x0C0C0000u;
+        // rule entry offset (2 * (x * Sp + y)) as a byte dot product
+        const uint32_t weights = ((2u * Sp) << (8 * cell)) | (2u << (8 * nbr));
         uint32_t scatter = 0;
         for (uint32_t b = 0; b < 4; ++b) {
             const uint32_t src = (b == cell) ? 4u : (b == nbr) ? 5u : b;
             scatter |= src << (8 * b);
         }
-        sel[i] = make_uint2(gather, scatter);
+        sel[i] = make_uint2(weights, scatter);
     }
     const uint32_t n = 3 * Sp * Sp;
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
@@ -162,14 +163,14 @@ template <class Ctx>
 __device__ __forceinline__ uint32_t block_update_sel(uint32_t B, uint32_t w,
                                                      uint2 s, const Ctx &c)
 {
-    const uint32_t xy = perm(B, B, s.x);
     // select values, not lvalues (an lvalue ?: selects addresses and keeps
     // the context in scratch memory)
     const uint32_t b1 = c.B1, b2 = c.B2, b3 = c.B3;
     uint32_t base = (w <= c.W2) ? b2 : b3;
     base = (w <= c.W1) ? b1 : base;
     if constexpr (Ctx::kProbabilistic) {
-        const uint32_t ai = __builtin_amdgcn_udot4(xy, c.abw, 0u, false);
+        // 4 * (x * Sp + y): the pair's A and B entries (u32)
+        const uint32_t ai = 2u * __builtin_amdgcn_udot4(B, s.x, 0u, false);
         const uint32_t A = *reinterpret_cast<const uint32_t *>(c.ab + ai);
         const uint32_t Bt =
             *reinterpret_cast<const uint32_t *>(c.ab + c.boff + ai);
@@ -178,7 +179,7 @@ __device__ __forceinline__ uint32_t block_update_sel(uint32_t B, uint32_t w,
         const uint32_t o = c.Bo + ((v >= A) ? so : zero) + ((v >= Bt) ? so : zero);
         base = (base == c.Bsel) ? o : base;
     }
-    const uint32_t off = __builtin_amdgcn_udot4(xy, c.dotw, base, false);
+    const uint32_t off = __builtin_amdgcn_udot4(B, s.x, base, false);
     const uint32_t out = *reinterpret_cast<const uint16_t *>(c.rule + off);
     return perm(out, B, s.y);
 }
@@ -302,6 +303,23 @@ __device__ __forceinline__ QuadRows quad_load(const uint8_t *lat, uint32_t pa,
                     __builtin_amdgcn_alignbyte(xa, ra.y, 1),
                     __builtin_amdgcn_alignbyte(rc.y, rc.x, 1),
                     __builtin_amdgcn_alignbyte(xc, rc.y, 1)};
+}
+
+// A quad of an even-offset pass (ox = 0) read from a copy of the region
+// stored one column to the right of 8-byte alignment: its window starts at
+// byte -1 of the aligned segment at pa.  The column before the segment is
+// byte 3 of the dword at pa - 4.
+__device__ __forceinline__ QuadRows quad_load_left(const uint8_t *lat,
+                                                   uint32_t pa, uint32_t LS)
+{
+    const uint2 ra = *reinterpret_cast<const uint2 *>(lat + pa);
+    const uint2 rc = *reinterpret_cast<const uint2 *>(lat + pa + LS);
+    const uint32_t ya = *reinterpret_cast<const uint32_t *>(lat + pa - 4);
+    const uint32_t yc = *reinterpret_cast<const uint32_t *>(lat + pa + LS - 4);
+    return QuadRows{__builtin_amdgcn_alignbyte(ra.x, ya, 3),
+                    __builtin_amdgcn_alignbyte(ra.y, ra.x, 3),
+                    __builtin_amdgcn_alignbyte(rc.x, yc, 3),
+                    __builtin_amdgcn_alignbyte(rc.y, rc.x, 3)};
 }
 
 __device__ __forceinline__ void quad_store(uint8_t *lat, uint32_t pa,

@@ -232,6 +232,25 @@ __device__ inline TileList tile_list(const TileGeom &G, uint32_t ty,
     return T;
 }
 
+// The list walk keeps two copies of the region in LDS: buffer 0 (column c
+// of row r at r * LS + c, as every other phase uses it) and buffer 1, the
+// same one column to the right of 8-byte alignment (column c at byte
+// r * LS + c - 1 of `lat1`), so that the windows of odd-offset quads
+// (columns 8j+1 .. 8j+8) are aligned there.  A pass reads the buffer the
+// previous pass wrote and writes the buffer in which its own windows are
+// aligned (buffer ox), except that the last pass of an MCS writes buffer 0
+// for the halo exchange.  Every write of a pass but that one is then an
+// aligned 8-byte store; only reads after a change of parity (and the last
+// pass when odd) are misaligned.  A pass that changes buffers leaves the
+// cells its quads do not cover (column 0 when ox = 1, the first and last
+// rows when oy = 1) stale in the buffer it writes.  That cannot reach the
+// tile's interior: a block update moves information by one cell per pass,
+// so a value left at the region's edge after pass p (0..3) of an MCS moves
+// at most 3 - p cells inward before the MCS ends, and the halo (4 rows, 8
+// columns) is gathered anew after every MCS.  The interior, the counts and
+// the published border strips are those of an in-place pass, byte for
+// byte.
+//
 // The Philox words and selector pairs of slot i + 1 are computed and loaded
 // before slot i is updated, so the selector lookups are in flight during
 // the update (prefetching the rows too measured no faster and needs more
@@ -239,19 +258,23 @@ __device__ inline TileList tile_list(const TileGeom &G, uint32_t ty,
 // slot 0 arrive in (rf, sf), and the pass leaves the next pass's there
 // before its barrier (the selector table is constant, the words depend on
 // the counter only).
-template <class Ctx>
-__device__ __forceinline__ void tile_pass_list(uint8_t *lat,
-                                               const TileGeom &G,
-                                               const TileList &T, uint32_t w,
-                                               uint32_t p, uint32_t t,
-                                               uint32_t replica, uint32_t k0,
-                                               uint32_t k1, const Ctx &qc,
-                                               Words &rf, QuadSel &sf)
+template <bool kOdd, bool kSrc1, bool kDst1, class Ctx>
+__device__ __forceinline__ void tile_pass_list_db(uint8_t *lat, uint8_t *lat1,
+                                                  const TileGeom &G,
+                                                  const TileList &T,
+                                                  uint32_t w, uint32_t p,
+                                                  uint32_t t,
+                                                  uint32_t replica,
+                                                  uint32_t k0, uint32_t k1,
+                                                  const Ctx &qc, Words &rf,
+                                                  QuadSel &sf)
 {
     const uint32_t LS = G.LS();
-    const uint32_t ox = w & 1u, oy = (w >> 1) & 1u;
+    const uint32_t oy = (w >> 1) & 1u;
     const uint32_t nq = ((G.RH() - oy) >> 1) * ((G.TW + 16) >> 3);
     const uint32_t ctr2 = (kTagPass << 8) | p, dy = oy * LS;
+    const uint8_t *src = kSrc1 ? lat1 : lat;
+    uint8_t *dst = kDst1 ? lat1 : lat;
     bool v[kListSlots];
     QuadRows q[kListSlots];
     Words r[kListSlots];
@@ -263,8 +286,15 @@ __device__ __forceinline__ void tile_pass_list(uint8_t *lat,
     qs[0] = sf;
 #pragma unroll
     for (uint32_t i = 0; i < kListSlots; ++i) {
-        if (v[i])
-            q[i] = quad_load(lat, T.pa[i] + dy, LS, ox);
+        const uint32_t pa = T.pa[i] + dy;
+        if (v[i]) {
+            if (kOdd == kSrc1) // aligned in the source buffer
+                q[i] = quad_load(src, pa, LS, 0u);
+            else if (kOdd) // buffer 0, window at +1
+                q[i] = quad_load(src, pa, LS, 1u);
+            else // buffer 1, window at -1
+                q[i] = quad_load_left(src, pa, LS);
+        }
         if (i + 1 < kListSlots && v[i + 1]) {
             r[i + 1] = philox(T.c0[i + 1], t, ctr2, replica, k0, k1);
             qs[i + 1] = quad_sel(r[i + 1], qc);
@@ -272,7 +302,8 @@ __device__ __forceinline__ void tile_pass_list(uint8_t *lat,
         if (v[i]) {
             quad_update_sel(q[i].a0, q[i].a1, q[i].c0, q[i].c1, r[i], qs[i],
                             qc);
-            quad_store(lat, T.pa[i] + dy, LS, ox, q[i]);
+            // aligned unless an odd pass writes buffer 0
+            quad_store(dst, pa, LS, (kOdd && !kDst1) ? 1u : 0u, q[i]);
         }
     }
     if (p < 3) { // the next pass's first slot, before the barrier
@@ -281,8 +312,37 @@ __device__ __forceinline__ void tile_pass_list(uint8_t *lat,
     }
 }
 
+// One pass of the list walk with word w (offsets), the lattice in buffer 1
+// when cur1; returns where the pass left it.  lat1: buffer 1 as above (an
+// 8-aligned address, RH * LS bytes from byte -1 on).
 template <class Ctx>
-__device__ __forceinline__ void tile_mcs_list(uint8_t *lat, const TileGeom &G,
+__device__ __forceinline__ bool tile_pass_list(uint8_t *lat, uint8_t *lat1,
+                                               const TileGeom &G,
+                                               const TileList &T, uint32_t w,
+                                               uint32_t p, bool cur1,
+                                               uint32_t t, uint32_t replica,
+                                               uint32_t k0, uint32_t k1,
+                                               const Ctx &qc, Words &rf,
+                                               QuadSel &sf)
+{
+    const bool odd = w & 1u, dst1 = odd && p < 3;
+#define ESCG_PASS(O, S1, D1)                                                  \
+    tile_pass_list_db<O, S1, D1>(lat, lat1, G, T, w, p, t, replica, k0, k1,  \
+                                 qc, rf, sf)
+    if (!odd)
+        cur1 ? ESCG_PASS(false, true, false) : ESCG_PASS(false, false, false);
+    else if (dst1)
+        cur1 ? ESCG_PASS(true, true, true) : ESCG_PASS(true, false, true);
+    else
+        cur1 ? ESCG_PASS(true, true, false) : ESCG_PASS(true, false, false);
+#undef ESCG_PASS
+    return dst1;
+}
+
+// One MCS of the list walk; the lattice is in buffer 0 before and after.
+template <class Ctx>
+__device__ __forceinline__ void tile_mcs_list(uint8_t *lat, uint8_t *lat1,
+                                              const TileGeom &G,
                                               const TileList &T, uint32_t t,
                                               uint32_t replica, uint32_t k0,
                                               uint32_t k1, const Ctx &qc)
@@ -291,10 +351,14 @@ __device__ __forceinline__ void tile_mcs_list(uint8_t *lat, const TileGeom &G,
         philox_uniform(0u, t, kTagOffset << 8, replica, k0, k1);
     Words rf = philox(T.c0[0], t, kTagPass << 8, replica, k0, k1);
     QuadSel sf = quad_sel(rf, qc); // slot 0 of pass 0
+    bool cur1 = false;
+    // unrolled (the passes then know p, and pass 0 reads buffer 0): 3.5 %
+    // faster than one copy of each kind of pass in a loop, at 14 copies
 #pragma unroll
     for (uint32_t p = 0; p < 4; ++p) {
-        tile_pass_list(lat, G, T, __builtin_amdgcn_readfirstlane(off.w[p]),
-                       p, t, replica, k0, k1, qc, rf, sf);
+        const uint32_t wp = __builtin_amdgcn_readfirstlane(off.w[p]);
+        cur1 = tile_pass_list(lat, lat1, G, T, wp, p, cur1, t, replica, k0,
+                              k1, qc, rf, sf);
         __syncthreads();
     }
 }

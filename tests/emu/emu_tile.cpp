@@ -5,6 +5,7 @@
 #include <vector>
 #include <cstdlib>
 emu_dim3 threadIdx, blockDim, blockIdx, gridDim;
+static bool bad_buffer = false;  // a list MCS left the lattice in buffer 1
 using namespace escg;
 extern "C" void orc_o2_run(uint32_t L, uint32_t S, const uint8_t *D, double ex, double sel, double rep,
   uint64_t seed, uint32_t replica, int rounds, int nbhd, const double *P, uint32_t mcs0, uint32_t n_mcs, uint8_t *grid, uint32_t *counts);
@@ -27,14 +28,20 @@ static void emu_tile_mcs(uint8_t *lat, const TileGeom &G, uint32_t ty, uint32_t 
 static void emu_tile_mcs_list(uint8_t *lat, const TileGeom &G, uint32_t ty, uint32_t tx, uint32_t t,
                               uint32_t rep, uint32_t k0, uint32_t k1, const QuadCtx &qc, uint32_t bd) {
   const Words off = philox(0u, t, kTagOffset << 8, rep, k0, k1);
+  uint8_t *lat1 = lat + G.region_bytes() + 8;  // the second region buffer
   blockDim.x = bd;
-  for (uint32_t p = 0; p < 4; ++p)
+  bool cur1 = false;
+  for (uint32_t p = 0; p < 4; ++p) {
+    bool next = false;
     for (threadIdx.x = 0; threadIdx.x < bd; ++threadIdx.x) {
       const TileList TL = tile_list(G, ty, tx);
       Words rf = philox(TL.c0[0], t, (kTagPass << 8) | p, rep, k0, k1);
       QuadSel sf = quad_sel(rf, qc);
-      tile_pass_list(lat, G, TL, off.w[p], p, t, rep, k0, k1, qc, rf, sf);
+      next = tile_pass_list(lat, lat1, G, TL, off.w[p], p, cur1, t, rep, k0, k1, qc, rf, sf);
     }
+    cur1 = next;
+  }
+  if (cur1) { bad_buffer = true; }
   blockDim.x = 1; threadIdx.x = 0;
 }
 static uint32_t list_threads(const TileGeom &G) {
@@ -64,7 +71,7 @@ int main() {
     uint32_t T = G.TY * G.TX;
     std::vector<uint8_t> g(L * L); srand(L + S * 7 + T1);
     for (auto& v : g) v = rand() % (S + 1);
-    std::vector<std::vector<uint8_t>> sm(T, std::vector<uint8_t>(G.region_bytes() + 64, 0));
+    std::vector<std::vector<uint8_t>> sm(T, std::vector<uint8_t>(2 * G.region_bytes() + 64, 0));
     static LdsTables<8> T8; static LdsTables<32> T32;
     const size_t area = (size_t)T * G.slot_dwords();
     std::vector<uint32_t> exch(2 * area, 0);
@@ -146,6 +153,7 @@ int main() {
     if (out != ref) { bad++; size_t d = 0; for (size_t i = 0; i < out.size(); ++i) d += out[i] != ref[i];
       printf("MISMATCH L=%u TH=%u TW=%u S=%u rates=%g,%g,%g: %zu sites differ\n", L, c.TH, c.TW, S, r[0], r[1], r[2], d); }
   }
+  if (bad_buffer) printf("LIST MCS ENDED IN BUFFER 1\n");
   printf("%d/%d tiled cases ok\n", cases - bad, cases);
-  return bad != 0;
+  return bad != 0 || bad_buffer;
 }
