@@ -206,6 +206,21 @@ __device__ __forceinline__ QuadSel quad_sel(const Words &w, const Ctx &c)
     return q;
 }
 
+// The four blocks of a quad (block j = [a(2j), a(2j+1), c(2j), c(2j+1)] of
+// its window) updated in place, with the selector pairs already loaded.
+template <class Ctx>
+__device__ __forceinline__ void quad_blocks_update(uint32_t &b0, uint32_t &b1,
+                                                   uint32_t &b2, uint32_t &b3,
+                                                   const Words &w,
+                                                   const QuadSel &qs,
+                                                   const Ctx &c)
+{
+    b0 = block_update_sel(b0, w.w[0], qs.s[0], c);
+    b1 = block_update_sel(b1, w.w[1], qs.s[1], c);
+    b2 = block_update_sel(b2, w.w[2], qs.s[2], c);
+    b3 = block_update_sel(b3, w.w[3], qs.s[3], c);
+}
+
 // Row segments (8 bytes each, little-endian: byte k = column k of the
 // segment) -> four updated segments in place, with the selector pairs
 // already loaded.
@@ -221,10 +236,7 @@ __device__ __forceinline__ void quad_update_sel(uint32_t &a0, uint32_t &a1,
     uint32_t b1 = perm(a0, c0, 0x03020706u);
     uint32_t b2 = perm(a1, c1, 0x01000504u);
     uint32_t b3 = perm(a1, c1, 0x03020706u);
-    b0 = block_update_sel(b0, w.w[0], qs.s[0], c);
-    b1 = block_update_sel(b1, w.w[1], qs.s[1], c);
-    b2 = block_update_sel(b2, w.w[2], qs.s[2], c);
-    b3 = block_update_sel(b3, w.w[3], qs.s[3], c);
+    quad_blocks_update(b0, b1, b2, b3, w, qs, c);
     // back to rows
     a0 = perm(b1, b0, 0x05040100u);
     c0 = perm(b1, b0, 0x07060302u);
@@ -254,6 +266,62 @@ __device__ __forceinline__ void quad_even(uint8_t *lat, uint32_t pa,
     *reinterpret_cast<uint2 *>(lat + pc) = rc;
 }
 
+// Odd-offset quads (ox = 1): the window is columns 1..8 of the aligned
+// 8-byte segment at pa (and the same LS further for the bottom row), the
+// ninth column being the first of the next segment.  The blocks are built
+// straight from the aligned loads, ra / rc = columns 0..7 of the two rows
+// and x = (bottom ninth byte) | (top ninth byte) << 16:
+//   B0 = [a1 a2 c1 c2], B2 = [a5 a6 c5 c6]  one v_perm each,
+//   n = [a4 c4 a7 c7], B1 = [a3 a4 c3 c4], B3 = [a7 a8 c7 c8],
+// six v_perm in all (aligning the rows first and transposing them takes
+// eight).
+__device__ __forceinline__ void odd_blocks(uint2 ra, uint2 rc, uint32_t x,
+                                           uint32_t &b0, uint32_t &b1,
+                                           uint32_t &b2, uint32_t &b3)
+{
+    b0 = perm(ra.x, rc.x, 0x02010605u);
+    b2 = perm(ra.y, rc.y, 0x02010605u);
+    const uint32_t m = perm(ra.x, rc.x, 0x0C0C0307u); // [a3 c3 0 0]
+    const uint32_t n = perm(ra.y, rc.y, 0x03070004u); // [a4 c4 a7 c7]
+    b1 = perm(n, m, 0x05010400u);
+    b3 = perm(x, n, 0x04030602u);
+}
+
+// The ninth bytes of an odd quad's two rows as one dword (bottom in byte
+// 0, top in byte 2): each byte load fills one half of it.
+__device__ __forceinline__ uint32_t odd_ninth(const uint8_t *lat, uint32_t ea,
+                                              uint32_t ec)
+{
+    return (uint32_t)lat[ec] | ((uint32_t)lat[ea] << 16);
+}
+
+// Writes an odd quad's updated blocks back as columns 1..8 of the two rows
+// (b8 at +1, b16 at +2, b32 at +4, b8 at the ninth byte ea / ec): per row
+// one v_perm gives [c1 - c2 c3] (b8 from bits 0-7, b16 from bits 16-31),
+// one gives [c5 c6 c8 c7] (the ninth byte from bits 16-23) and one more
+// [c4 c5 c6 c7]; six v_perm in all.
+__device__ __forceinline__ void odd_store(uint8_t *lat, uint32_t pa,
+                                          uint32_t pc, uint32_t ea,
+                                          uint32_t ec, uint32_t b0,
+                                          uint32_t b1, uint32_t b2,
+                                          uint32_t b3)
+{
+    const uint32_t a1 = perm(b1, b0, 0x04010C00u);  // [a1 - a2 a3]
+    const uint32_t a5 = perm(b3, b2, 0x04050100u);  // [a5 a6 a8 a7]
+    const uint32_t a4 = perm(a5, b1, 0x07050401u);  // [a4 a5 a6 a7]
+    const uint32_t c1 = perm(b1, b0, 0x06030C02u);  // [c1 - c2 c3]
+    const uint32_t c5 = perm(b3, b2, 0x06070302u);  // [c5 c6 c8 c7]
+    const uint32_t c4 = perm(c5, b1, 0x07050403u);  // [c4 c5 c6 c7]
+    lat[pa + 1] = (uint8_t)a1;
+    *reinterpret_cast<uint16_t *>(lat + pa + 2) = (uint16_t)(a1 >> 16);
+    *reinterpret_cast<uint32_t *>(lat + pa + 4) = a4;
+    lat[ea] = (uint8_t)(a5 >> 16);
+    lat[pc + 1] = (uint8_t)c1;
+    *reinterpret_cast<uint16_t *>(lat + pc + 2) = (uint16_t)(c1 >> 16);
+    *reinterpret_cast<uint32_t *>(lat + pc + 4) = c4;
+    lat[ec] = (uint8_t)(c5 >> 16);
+}
+
 // Quad whose columns start one byte after an 8-byte boundary (ox = 1):
 // pa / pc are the aligned addresses, ea / ec the addresses of the ninth byte
 // (the column after the 8-byte boundary, possibly wrapped by the caller).
@@ -265,23 +333,10 @@ __device__ __forceinline__ void quad_odd(uint8_t *lat, uint32_t pa,
 {
     const uint2 ra = *reinterpret_cast<const uint2 *>(lat + pa);
     const uint2 rc = *reinterpret_cast<const uint2 *>(lat + pc);
-    const uint32_t xa = lat[ea], xc = lat[ec];
-    uint32_t a0 = __builtin_amdgcn_alignbyte(ra.y, ra.x, 1);
-    uint32_t a1 = __builtin_amdgcn_alignbyte(xa, ra.y, 1);
-    uint32_t c0 = __builtin_amdgcn_alignbyte(rc.y, rc.x, 1);
-    uint32_t c1 = __builtin_amdgcn_alignbyte(xc, rc.y, 1);
-    quad_update(a0, a1, c0, c1, w, c);
-    // bytes 1..8 of the window: b8 at +1, b16 at +2, b32 at +4, b8 at +8
-    lat[pa + 1] = (uint8_t)a0;
-    *reinterpret_cast<uint16_t *>(lat + pa + 2) = (uint16_t)(a0 >> 8);
-    *reinterpret_cast<uint32_t *>(lat + pa + 4) =
-        __builtin_amdgcn_alignbyte(a1, a0, 3);
-    lat[ea] = (uint8_t)(a1 >> 24);
-    lat[pc + 1] = (uint8_t)c0;
-    *reinterpret_cast<uint16_t *>(lat + pc + 2) = (uint16_t)(c0 >> 8);
-    *reinterpret_cast<uint32_t *>(lat + pc + 4) =
-        __builtin_amdgcn_alignbyte(c1, c0, 3);
-    lat[ec] = (uint8_t)(c1 >> 24);
+    uint32_t b0, b1, b2, b3;
+    odd_blocks(ra, rc, odd_ninth(lat, ea, ec), b0, b1, b2, b3);
+    quad_blocks_update(b0, b1, b2, b3, w, quad_sel(w, c), c);
+    odd_store(lat, pa, pc, ea, ec, b0, b1, b2, b3);
 }
 
 // Load and store halves of quad_even / quad_odd (ox = 0 / 1, uniform), for
