@@ -193,10 +193,15 @@ def serving(args, torch, escg, workloads):
 
 def rps512(args, torch, escg, workloads):
     """The L = 512 RPS workload (10,000 MCS, counts every MCS): init and
-    the whole run per repetition, on the route the library picks."""
+    the whole run per repetition, on the route the library picks, with the
+    autotuned tile shape where the cache has one."""
+    from paper_2508_16639_amd import autotune
     w = workloads.RPS512
     p = escg.Params(L=w.L, S=w.S, dom=escg.circulant_dom(w.S, w.K), ex=w.ex,
                     sel=w.sel, rep=w.rep, seed=w.seed, replica=w.replica)
+    tuned = autotune.apply(torch, p, "persistent")
+    autotuned = tuned is not p
+    p = tuned
     lat = torch.empty(w.L * w.L, dtype=torch.uint8, device="cuda")
     cnt = torch.empty((w.mcs + 1) * (w.S + 1), dtype=torch.int32,
                       device="cuda")
@@ -215,7 +220,8 @@ def rps512(args, torch, escg, workloads):
     return {"workload": "rps_L512_M1e-4_10000mcs (counts every MCS)",
             "site_updates_per_s": float(w.L) ** 2 * w.mcs / wall,
             "ms_per_run": wall * 1e3, "route": escg.last_route(),
-            "reps": reps}
+            "tile_TH_TW_threads": escg.tile_plan(p, True),
+            "tile_shape_autotuned": autotuned, "reps": reps}
 
 
 def host_cpu() -> str:
