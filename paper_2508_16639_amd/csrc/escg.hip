@@ -250,6 +250,11 @@ __device__ void run_job_lds(const JobDev &J, uint8_t *base, uint8_t *smem,
     const auto qc = make_quad_ctx<kProb>(TB, J.T1, J.T2);
     const LdsWalk W = lds_walk(L, LS);
     const uint32_t ndw = (LS * L) >> 2;
+    // the Philox heads of this thread's quads, once per job, when they fit
+    const bool heads = lds_heads_fit(W, L);
+    LdsHeads H;
+    if (heads)
+        H = lds_heads(W, J.replica, k1);
 
     // counts of the current state: S <= 7 into c[] (uniform, every wave),
     // else into the LDS row `row` of s_cnt; returns the stop test
@@ -288,7 +293,11 @@ __device__ void run_job_lds(const JobDev &J, uint8_t *base, uint8_t *smem,
         const uint32_t nxt = cur ^ 1u;
         if (!kPacked && tid < 32)
             s_cnt[nxt * 32 + tid] = 0;
-        lds_mcs(lat, L, LS, J.mcs0 + t, J.replica, k0, k1, qc, W);
+        if (heads)
+            lds_mcs<true>(lat, L, LS, J.mcs0 + t, J.replica, k0, k1, qc, W,
+                          &H);
+        else
+            lds_mcs(lat, L, LS, J.mcs0 + t, J.replica, k0, k1, qc, W);
         ++t;
         if constexpr (kPacked) {
             if (ns == 4) {

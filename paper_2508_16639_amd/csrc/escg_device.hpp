@@ -114,6 +114,55 @@ __device__ __forceinline__ Words philox(uint32_t c0, uint32_t c1, uint32_t c2,
     o.w[0] = c0; o.w[1] = c1; o.w[2] = c2; o.w[3] = c3;
     return o;
 }
+
+// What philox() computes from the varying word c0 before the other counter
+// words enter: with c1 (the MCS) and c2 (tag and pass) uniform and c3 (the
+// replica) and the key fixed for a job, the first round's product of c0
+// and the second round's product of the first round's c2 depend on c0, c3
+// and k1 only.  A quad visited every pass of every MCS keeps them.
+struct PhiloxHead {
+    uint32_t h, l; // the second round's product kMulB * c2 (high, low)
+    uint32_t y;    // low half of the first round's product kMulA * c0
+};
+
+__device__ __forceinline__ PhiloxHead philox_head(uint32_t c0, uint32_t c3,
+                                                  uint32_t k1)
+{
+    const uint64_t pa = (uint64_t)kMulA * c0;
+    const uint32_t x = (uint32_t)(pa >> 32) ^ c3 ^ k1; // the first round's c2
+    const uint64_t pb = (uint64_t)kMulB * x;
+    return PhiloxHead{(uint32_t)(pb >> 32), (uint32_t)pb, (uint32_t)pa};
+}
+
+// philox(c0, c1, c2, c3, k0, k1) for hd = philox_head(c0, c3, k1).
+__device__ __forceinline__ Words philox_from_head(const PhiloxHead &hd,
+                                                  uint32_t c1, uint32_t c2,
+                                                  uint32_t k0, uint32_t k1)
+{
+    static_assert(kPhiloxRounds >= 3, "the first three rounds are unrolled");
+    // first round, uniform half: the new c0 and c1
+    const uint64_t pb1 = (uint64_t)kMulB * c2;
+    const uint32_t u0 = (uint32_t)(pb1 >> 32) ^ c1 ^ k0;
+    const uint32_t u1 = (uint32_t)pb1;
+    k0 += kWeylA;
+    k1 += kWeylB;
+    // second round: its product of c0 is uniform, that of c2 is the head's
+    const uint64_t pa2 = (uint64_t)kMulA * u0;
+    uint32_t c0 = hd.h ^ u1 ^ k0;
+    uint32_t c2n = (uint32_t)(pa2 >> 32) ^ hd.y ^ k1;
+    c1 = hd.l;
+    uint32_t c3 = (uint32_t)pa2;
+    c2 = c2n;
+    k0 += kWeylA;
+    k1 += kWeylB;
+    ESCG_PHILOX_ROUND(xor3_vvs, xor3_c); // c0, c1, c2 vary; c3 uniform
+#pragma unroll
+    for (int r = 3; r < kPhiloxRounds; ++r)
+        ESCG_PHILOX_ROUND(xor3_vvs, xor3_vvs);
+    Words o;
+    o.w[0] = c0; o.w[1] = c1; o.w[2] = c2; o.w[3] = c3;
+    return o;
+}
 #undef ESCG_PHILOX_ROUND
 
 // The same rounds for a counter and key that are uniform across the wave

@@ -71,14 +71,72 @@ __device__ inline LdsWalk lds_walk(uint32_t L, uint32_t LS)
     return W;
 }
 
-// Pass p of MCS t for this thread's quads; w = word p of the MCS's offset
-// draw (ox = bit 0, oy = bit 1, uniform).
+// The Philox heads (philox_head) of a thread's quads, the k-th at block row
+// by0 + k * rstep, when a thread has at most kLdsHeads quads (every L when
+// blockDim / ceil(L/8) * kLdsHeads >= L/2, e.g. L <= 256 at 512 threads):
+// a quad's counter word, the replica and the key are the same every pass of
+// every MCS of the job, so the heads are computed once per job.
+constexpr uint32_t kLdsHeads = 8;
+
+struct LdsHeads {
+    PhiloxHead q[kLdsHeads];
+};
+
+__device__ inline bool lds_heads_fit(const LdsWalk &W, uint32_t L)
+{
+    return W.rstep * kLdsHeads >= (L >> 1);
+}
+
+__device__ inline LdsHeads lds_heads(const LdsWalk &W, uint32_t replica,
+                                     uint32_t k1)
+{
+    LdsHeads H;
+#pragma unroll
+    for (uint32_t k = 0; k < kLdsHeads; ++k)
+        H.q[k] = philox_head(W.c0 + k * W.cstep, replica, k1);
+    return H;
+}
+
+// One quad of pass (ox, oy) at block row by, top row at LDS offset pa.
 template <class Ctx>
+__device__ __forceinline__ void lds_quad(uint8_t *lat, uint32_t L,
+                                         uint32_t LS, const LdsWalk &W,
+                                         uint32_t ox, uint32_t oy,
+                                         uint32_t by, uint32_t pa,
+                                         const Words &r, const Ctx &qc)
+{
+    const uint32_t Lb = L >> 1;
+    // the bottom row of the last block row wraps to row 0
+    const uint32_t pc = (oy && by == Lb - 1u) ? W.col : pa + LS;
+    if (W.full) {
+        if (ox == 0)
+            quad_even(lat, pa, pc, r, qc);
+        else
+            quad_odd(lat, pa, pc, pa + W.dnext, pc + W.dnext, r, qc);
+    } else {
+        // last quad of a row with fewer than four blocks
+        const uint32_t rowA = pa - W.col, rowC = pc - W.col;
+        for (uint32_t j = 0; j < 4; ++j) {
+            if (W.col / 2u + j < Lb) {
+                const uint32_t x0 = W.col + 2u * j + ox;
+                const uint32_t x1 = (x0 + 1u == L) ? 0u : x0 + 1u;
+                block_bytes(lat, rowA + x0, rowA + x1, rowC + x0, rowC + x1,
+                            pick(r, j), qc);
+            }
+        }
+    }
+}
+
+// Pass p of MCS t for this thread's quads; w = word p of the MCS's offset
+// draw (ox = bit 0, oy = bit 1, uniform).  With heads (kHeads: H holds the
+// thread's quads' Philox heads, lds_heads_fit) the draws start from them.
+template <bool kHeads = false, class Ctx>
 __device__ __forceinline__ void lds_pass(uint8_t *lat, uint32_t L,
                                          uint32_t LS, const LdsWalk &W,
                                          uint32_t w, uint32_t p, uint32_t t,
                                          uint32_t replica, uint32_t k0,
-                                         uint32_t k1, const Ctx &qc)
+                                         uint32_t k1, const Ctx &qc,
+                                         const LdsHeads *H = nullptr)
 {
     const uint32_t Lb = L >> 1;
     const uint32_t ox = w & 1u, oy = (w >> 1) & 1u;
@@ -86,46 +144,48 @@ __device__ __forceinline__ void lds_pass(uint8_t *lat, uint32_t L,
     if (!W.active)
         return;
     uint32_t c0 = W.c0, pa = W.pa0 + oy * LS;
-    for (uint32_t by = W.by0; by < Lb; by += W.rstep) {
-        const Words r = philox(c0, t, ctr2, replica, k0, k1);
-        // the bottom row of the last block row wraps to row 0
-        const uint32_t pc = (oy && by == Lb - 1u) ? W.col : pa + LS;
-        if (W.full) {
-            if (ox == 0)
-                quad_even(lat, pa, pc, r, qc);
-            else
-                quad_odd(lat, pa, pc, pa + W.dnext, pc + W.dnext, r, qc);
-        } else {
-            // last quad of a row with fewer than four blocks
-            const uint32_t rowA = pa - W.col, rowC = pc - W.col;
-            for (uint32_t j = 0; j < 4; ++j) {
-                if (W.col / 2u + j < Lb) {
-                    const uint32_t x0 = W.col + 2u * j + ox;
-                    const uint32_t x1 = (x0 + 1u == L) ? 0u : x0 + 1u;
-                    block_bytes(lat, rowA + x0, rowA + x1, rowC + x0,
-                                rowC + x1, pick(r, j), qc);
-                }
-            }
+    if constexpr (kHeads) {
+#pragma unroll
+        for (uint32_t k = 0; k < kLdsHeads; ++k) {
+            const uint32_t by = W.by0 + k * W.rstep;
+            if (by >= Lb)
+                break;
+            const Words r = philox_from_head(H->q[k], t, ctr2, k0, k1);
+            lds_quad(lat, L, LS, W, ox, oy, by, pa, r, qc);
+            pa += W.pstep;
         }
-        pa += W.pstep;
-        c0 += W.cstep;
+    } else {
+        for (uint32_t by = W.by0; by < Lb; by += W.rstep) {
+            const Words r = philox(c0, t, ctr2, replica, k0, k1);
+            lds_quad(lat, L, LS, W, ox, oy, by, pa, r, qc);
+            pa += W.pstep;
+            c0 += W.cstep;
+        }
     }
 }
 
 // One MCS (four passes) on an L x L lattice held whole in LDS with row
 // stride LS.
-template <class Ctx>
+template <bool kHeads = false, class Ctx>
 __device__ __forceinline__ void lds_mcs(uint8_t *lat, uint32_t L, uint32_t LS,
                                         uint32_t t, uint32_t replica,
                                         uint32_t k0, uint32_t k1,
-                                        const Ctx &qc, const LdsWalk &W)
+                                        const Ctx &qc, const LdsWalk &W,
+                                        const LdsHeads *H = nullptr)
 {
     const Words off =
         philox_uniform(0u, t, kTagOffset << 8, replica, k0, k1);
-#pragma unroll
+    // a loop, not unrolled: with the heads the pass body holds kLdsHeads
+    // quads, and four copies of it would not be inlined (p picks its word by
+    // selects, not by indexing, which would keep the words in scratch)
+#pragma unroll 1
     for (uint32_t p = 0; p < 4; ++p) {
-        lds_pass(lat, L, LS, W, __builtin_amdgcn_readfirstlane(off.w[p]), p,
-                 t, replica, k0, k1, qc);
+        const uint32_t wp = p == 0   ? off.w[0]
+                            : p == 1 ? off.w[1]
+                            : p == 2 ? off.w[2]
+                                     : off.w[3];
+        lds_pass<kHeads>(lat, L, LS, W, __builtin_amdgcn_readfirstlane(wp), p,
+                         t, replica, k0, k1, qc, H);
         __syncthreads();
     }
 }

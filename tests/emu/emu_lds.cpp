@@ -54,10 +54,21 @@ int main(int argc, char** argv) {
     blockDim.x = nts[cases % 3];
     for (uint32_t t = 0; t < n; ++t) {
       const Words off = philox(0u, mcs0 + t, kTagOffset << 8, rep, (uint32_t)seed, (uint32_t)(seed >> 32));
+      // every other case starts the draws from the per-quad Philox heads
+      // where a thread's quads fit them
       for (uint32_t p = 0; p < 4; ++p)
-        for (threadIdx.x = 0; threadIdx.x < blockDim.x; ++threadIdx.x)
-          if (prob) lds_pass(lat, L, LS, lds_walk(L, LS), off.w[p], p, mcs0 + t, rep, (uint32_t)seed, (uint32_t)(seed >> 32), qcp);
-          else lds_pass(lat, L, LS, lds_walk(L, LS), off.w[p], p, mcs0 + t, rep, (uint32_t)seed, (uint32_t)(seed >> 32), qc);
+        for (threadIdx.x = 0; threadIdx.x < blockDim.x; ++threadIdx.x) {
+          const LdsWalk W = lds_walk(L, LS);
+          const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+          if ((cases & 1) && lds_heads_fit(W, L)) {
+            const LdsHeads H = lds_heads(W, rep, k1);
+            if (prob) lds_pass<true>(lat, L, LS, W, off.w[p], p, mcs0 + t, rep, k0, k1, qcp, &H);
+            else lds_pass<true>(lat, L, LS, W, off.w[p], p, mcs0 + t, rep, k0, k1, qc, &H);
+          } else {
+            if (prob) lds_pass(lat, L, LS, W, off.w[p], p, mcs0 + t, rep, k0, k1, qcp);
+            else lds_pass(lat, L, LS, W, off.w[p], p, mcs0 + t, rep, k0, k1, qc);
+          }
+        }
     }
     blockDim.x = 1; threadIdx.x = 0;
     std::vector<uint8_t> ref = g;
