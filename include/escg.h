@@ -54,7 +54,7 @@ typedef int32_t escg_status;
 #define ESCG_EINVAL        (-1) /* invalid argument; nothing enqueued        */
 #define ESCG_ENOMEM        (-2) /* device scratch allocation failed           */
 #define ESCG_EDEVICE       (-3) /* a HIP call failed                          */
-#define ESCG_EUNSUPPORTED  (-4) /* valid request this build cannot run        */
+#define ESCG_EUNSUPPORTED  (-4) /* valid request this library cannot run      */
 #define ESCG_ETIMEOUT      (-5) /* a device wait exceeded its spin bound      */
 
 #define ESCG_MAX_SPECIES   31u

@@ -11,8 +11,8 @@
 // A measurement helper, not part of the library (nothing builds or loads it
 // automatically).  Build and run from the repository root:
 //   hipcc --offload-arch=gfx950 -O3 -Xclang -target-feature -Xclang
-//     -packed-fp32-ops tests/microbench/valu_rates.hip -o gpurun_out/valu_rates
-//   ./gpurun_out/valu_rates
+//     -packed-fp32-ops tests/microbench/valu_rates.hip -o /tmp/valu_rates
+//   /tmp/valu_rates
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
