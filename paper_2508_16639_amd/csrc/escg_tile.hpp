@@ -282,6 +282,10 @@ __device__ __forceinline__ void tile_pass_list_db(uint8_t *lat, uint8_t *lat1,
 #pragma unroll
     for (uint32_t i = 0; i < kListSlots; ++i)
         v[i] = threadIdx.x + i * blockDim.x < nq;
+    // the waves with a quad in every slot issue first (wave priority), so
+    // that the waves of a SIMD reach the pass barrier closer together
+    if (v[kListSlots - 1])
+        __builtin_amdgcn_s_setprio(1);
     r[0] = rf;
     qs[0] = sf;
 #pragma unroll
@@ -306,6 +310,7 @@ __device__ __forceinline__ void tile_pass_list_db(uint8_t *lat, uint8_t *lat1,
             quad_store(dst, pa, LS, (kOdd && !kDst1) ? 1u : 0u, q[i]);
         }
     }
+    __builtin_amdgcn_s_setprio(0);
     if (p < 3) { // the next pass's first slot, before the barrier
         rf = philox(T.c0[0], t, (kTagPass << 8) | (p + 1), replica, k0, k1);
         sf = quad_sel(rf, qc);

@@ -43,6 +43,7 @@ inline unsigned min(unsigned a, unsigned b) { return a < b ? a : b; }
 template <class T> T atomicAdd(T* p, T v) { T o = *p; *p += v; return o; }
 #define __HIP_MEMORY_SCOPE_AGENT 3
 inline void __builtin_amdgcn_s_sleep(int) {}
+inline void __builtin_amdgcn_s_setprio(int) {}
 template <class T> inline void __hip_atomic_store(T* p, T v, int, int) { *p = v; }
 template <class T> inline T __hip_atomic_load(T* p, int, int) { return *p; }
 // Cross-lane operations have no meaning when threads run one at a time; the
